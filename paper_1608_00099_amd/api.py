@@ -1,0 +1,290 @@
+"""Torch-facing helpers over the C ABI.
+
+PyTorch supplies device memory and the current stream; every step of the
+computation runs in libtriot's kernels.  Operands are contiguous CUDA/HIP
+tensors viewed as row-major parent buffers; ``shape`` and ``base`` arguments
+describe windows into them (Section 4 of the paper: slices with a bias).
+"""
+from __future__ import annotations
+
+import threading
+
+import torch
+
+from . import _lib as L
+from ._lib import TriotError
+
+_ws_lock = threading.Lock()
+_ws_cache: dict = {}
+
+
+def _stream(dev: torch.device):
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _check(st: int, what: str):
+    if st != L.OK:
+        raise TriotError(st, what)
+
+
+def _prep(tensors, shapes):
+    dev = None
+    for t in tensors:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("triot operands must be GPU tensors")
+        if not t.is_contiguous():
+            raise ValueError("triot operands must be contiguous parent buffers")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError("all operands must live on one device")
+    if shapes is None:
+        shapes = [tuple(t.shape) for t in tensors]
+    return dev, [tuple(int(v) for v in s) for s in shapes]
+
+
+def _ptr(t):
+    return t.data_ptr() if (t is not None and t.numel() > 0) else 0
+
+
+def apply(op, tensors, shapes=None, counter=None, bases=None, params=None, out=None,
+          workspace=None, what="triot_apply"):
+    """Run one co-iteration on the current stream (see include/triot.h)."""
+    dev, shapes = _prep(tensors, shapes)
+    d = len(shapes[0]) if shapes else 0
+    if any(len(s) != d for s in shapes):
+        raise ValueError("all operand shapes must have the same dimension")
+    ws_ptr, ws_bytes = 0, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    st = L.triot_apply(op, len(tensors), d, shapes, counter, [_ptr(t) for t in tensors], bases,
+                       params, out.data_ptr() if out is not None else 0, ws_ptr, ws_bytes,
+                       _stream(dev))
+    _check(st, what)
+
+
+def workspace_for(op, shapes, counter, dev):
+    """A zero-initialised workspace, cached per (device, stream, size)."""
+    d = len(shapes[0]) if shapes else 0
+    nbytes = L.triot_workspace_size(op, len(shapes), d, shapes, counter)
+    if nbytes == 0:
+        return None
+    key = (dev, _stream(dev))
+    with _ws_lock:
+        ws = _ws_cache.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.zeros(max(nbytes, 4096), dtype=torch.uint8, device=dev)
+            _ws_cache[key] = ws
+    return ws
+
+
+# ---------------------------------------------------------------------------
+# Copies: zero-pad embedding and crop (Sections 1 and 3)
+# ---------------------------------------------------------------------------
+
+def _elem_params(t):
+    es = t.element_size()
+    if es not in (4, 8):
+        raise ValueError("copies move 4- or 8-byte elements")
+    return L.CopyParams(es)
+
+
+def copy_(dst, src, counter=None, dst_shape=None, src_shape=None, dst_base=0, src_base=0):
+    """dst[t] = src[t] for every tuple of ``counter`` (default: the shapes'
+    intersection)."""
+    if dst.element_size() != src.element_size():
+        raise ValueError("element sizes differ")
+    shapes = [tuple(dst_shape or dst.shape), tuple(src_shape or src.shape)]
+    apply(L.OP_COPY, [dst, src], shapes, counter, [dst_base, src_base], _elem_params(dst),
+          what="copy")
+    return dst
+
+
+def pad_embed_into(dst, x):
+    """Zero-pad embedding of x at the origin of a pre-zeroed dst (counter =
+    x's shape); only the counter points are written."""
+    return copy_(dst, x, counter=tuple(x.shape))
+
+
+def embed_fill_(dst, src, dst_shape=None, src_shape=None, src_base=0):
+    """Over all of dst: src where the tuple lies in src, +0.0 elsewhere."""
+    shapes = [tuple(dst_shape or dst.shape), tuple(src_shape or src.shape)]
+    apply(L.OP_EMBED_FILL, [dst, src], shapes, None, [0, src_base], _elem_params(dst),
+          what="embed_fill")
+    return dst
+
+
+def pad_embed(x, shape):
+    """A new tensor of ``shape`` holding x at the origin and zeros elsewhere,
+    written in one pass (the zero padding ahead of an FFT convolution)."""
+    out = torch.empty(tuple(shape), dtype=x.dtype, device=x.device)
+    return embed_fill_(out, x)
+
+
+def crop(x, shape):
+    """A new tensor with x's leading ``shape`` window (benchmark 1's copy)."""
+    out = torch.empty(tuple(shape), dtype=x.dtype, device=x.device)
+    return copy_(out, x, counter=tuple(shape))
+
+
+# ---------------------------------------------------------------------------
+# Element-wise products over shared tuples
+# ---------------------------------------------------------------------------
+
+def _f32(*ts):
+    for t in ts:
+        if t.dtype != torch.float32:
+            raise ValueError("arithmetic ops take float32 tensors")
+
+
+def mul_acc_(x, y, z, counter=None, shapes=None, bases=None):
+    """x[t] += y[t]*z[t] (two roundings) over counter (default: intersection)."""
+    _f32(x, y, z)
+    apply(L.OP_MUL_ACC, [x, y, z], shapes, counter, bases, what="mul_acc")
+    return x
+
+
+def mul_into(out, a, b, counter=None, shapes=None, bases=None):
+    _f32(out, a, b)
+    apply(L.OP_MUL, [out, a, b], shapes, counter, bases, what="mul")
+    return out
+
+
+def mul(a, b, counter=None):
+    """out[t] = a[t]*b[t] over counter (default: the shapes' intersection)."""
+    if counter is None:
+        counter = tuple(min(p, q) for p, q in zip(a.shape, b.shape))
+    out = torch.empty(tuple(counter), dtype=torch.float32, device=a.device)
+    return mul_into(out, a, b, counter=tuple(counter))
+
+
+def mul_adj(gout, a, b):
+    """Adjoint of out = a*b over the intersection I = gout's shape."""
+    _f32(gout, a, b)
+    ga = torch.empty_like(a)
+    gb = torch.empty_like(b)
+    apply(L.OP_MUL_ADJ, [ga, gb, gout, a, b], None, None, None, what="mul_adj")
+    return ga, gb
+
+
+# ---------------------------------------------------------------------------
+# Index-weighted moments (Algorithm 11) and their adjoint
+# ---------------------------------------------------------------------------
+
+def n_moments(d: int, cov: bool) -> int:
+    return 1 + d + (d * (d + 1) // 2 if cov else 0)
+
+
+def moments(p, cov=True, others=(), counter=None):
+    """(out32, out64): [M, E_0..E_{d-1}(, upper-triangle C)] of the weights
+    w(t) = p[t] * prod(others[k][t]) over counter (default: intersection)."""
+    tensors = [p] + list(others)
+    _f32(*tensors)
+    dev, shapes = _prep(tensors, None)
+    d = p.dim()
+    nout = n_moments(d, cov)
+    out32 = torch.empty(nout, dtype=torch.float32, device=dev)
+    out64 = torch.empty(nout, dtype=torch.float64, device=dev)
+    ws = workspace_for(L.OP_MOMENTS, shapes, counter, dev)
+    params = L.MomentsParams(L.MOMENTS_FIRST | (L.MOMENTS_COV if cov else 0), out64.data_ptr())
+    apply(L.OP_MOMENTS, tensors, shapes, counter, None, params, out=out32, workspace=ws,
+          what="moments")
+    return out32, out64
+
+
+def moments_adj(shape, mom64, gmom32, cov=True, device=None):
+    """g[t] = d loss / d w(t) for every t of ``shape``."""
+    dev = device or mom64.device
+    g = torch.empty(tuple(shape), dtype=torch.float32, device=dev)
+    gm = gmom32.contiguous()
+    params = L.MomentsAdjParams(L.MOMENTS_FIRST | (L.MOMENTS_COV if cov else 0),
+                                mom64.data_ptr(), gm.data_ptr())
+    apply(L.OP_MOMENTS_ADJ, [g], None, None, None, params, what="moments_adj")
+    return g
+
+
+def index(shapes, counter=None, bases=None, device="cuda"):
+    """int64 [n, N]: the offset of every counter tuple in every operand."""
+    shapes = [tuple(int(v) for v in s) for s in shapes]
+    n, d = len(shapes), len(shapes[0])
+    if counter is None:
+        counter = tuple(min(s[i] for s in shapes) for i in range(d))
+    N = 1
+    for c in counter:
+        N *= int(c)
+    out = torch.empty((n, N), dtype=torch.int64, device=device)
+    ptrs = [out.data_ptr()] + [0] * (n - 1)
+    st = L.triot_apply(L.OP_INDEX, n, d, shapes, counter, ptrs, bases, None, 0, 0, 0,
+                       _stream(out.device))
+    _check(st, "index")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Batched form and tuning
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """A batch handle: the planned work table and captured hipGraph of one
+    batch of independent co-iterations (replayed while the batch repeats)."""
+
+    def __init__(self):
+        st, self._h = L.triot_batch_create()
+        _check(st, "batch_create")
+
+    def close(self):
+        if self._h:
+            L.triot_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, op, items, elem_bytes=4):
+        """items: list of operand lists (contiguous GPU tensors); each item's
+        counter is the op's default (see include/triot.h)."""
+        if not items:
+            return
+        dev = items[0][0].device
+        marshalled = []
+        for ops in items:
+            shapes = [tuple(t.shape) for t in ops]
+            marshalled.append((len(shapes[0]), len(ops), shapes, None, [_ptr(t) for t in ops], None))
+        params = L.CopyParams(elem_bytes) if op in (L.OP_COPY, L.OP_EMBED_FILL) else None
+        st = L.triot_apply_batched(op, marshalled, params, self._h, _stream(dev))
+        _check(st, "apply_batched")
+
+    def info(self):
+        st, units, blocks, replayed = L.triot_batch_info(self._h)
+        _check(st, "batch_info")
+        return {"units": units, "blocks": blocks, "replayed": bool(replayed)}
+
+
+def autotune(op, tensors, shapes=None, counter=None, bases=None, params=None, cache_path=None):
+    """Pick the fastest launch schedule for this exact problem (runs the op
+    several times on the given buffers)."""
+    dev, shapes = _prep(tensors, shapes)
+    d = len(shapes[0])
+    st = L.triot_autotune(op, len(tensors), d, shapes, counter, [_ptr(t) for t in tensors], bases,
+                          params, 0, 0, 0, _stream(dev), cache_path)
+    _check(st, "autotune")
+
+
+def describe(op, shapes, counter=None, ptrs=None, bases=None, params=None):
+    """The launch plan triot_apply would use (no device work)."""
+    shapes = [tuple(int(v) for v in s) for s in shapes]
+    if ptrs is None:
+        ptrs = [(k + 1) << 40 for k in range(len(shapes))]
+    st, info = L.triot_plan_describe(op, len(shapes), len(shapes[0]), shapes, counter, ptrs, bases,
+                                     params)
+    _check(st, "plan_describe")
+    return {"kernel": info.kernel, "dims": info.dims,
+            "extents": [info.extents[i] for i in range(info.dims)], "vec": info.vec,
+            "high_axes": info.high_axes, "low_axes": info.low_axes, "box_rows": info.box_rows,
+            "units": info.units, "blocks": info.blocks, "threads": info.threads,
+            "unroll": info.unroll}

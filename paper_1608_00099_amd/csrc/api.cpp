@@ -1,0 +1,547 @@
+// C ABI of the co-iteration library: validation and planning on the host,
+// launches on the caller's stream, the batched form (a device work table
+// replayed through a captured hipGraph) and the schedule autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "launch.h"
+#include "plan.h"
+#include "triot.h"
+
+using namespace triot;
+
+namespace {
+
+int co_op_of(triot_op op)
+{
+    switch (op) {
+    case TRIOT_OP_COPY: return CO_COPY;
+    case TRIOT_OP_EMBED_FILL: return CO_FILL;
+    case TRIOT_OP_MUL_ACC: return CO_MUL_ACC;
+    case TRIOT_OP_MUL: return CO_MUL;
+    case TRIOT_OP_MUL_ADJ: return CO_MUL_ADJ;
+    case TRIOT_OP_INDEX: return CO_INDEX;
+    default: return -1;
+    }
+}
+
+// ---- schedule cache ---------------------------------------------------
+
+std::mutex g_mu;
+std::unordered_map<std::string, Sched> g_sched;
+bool g_loaded = false;
+
+void load_cache_file(const char *path)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return;
+    char line[8192];
+    while (std::fgets(line, sizeof line, f)) {
+        // {"key": "<key>", "vec": V, "unroll": U, "bpc": B, "rb": R, "pe": P}
+        char key[4096];
+        Sched s;
+        int n = std::sscanf(line,
+                            " {\"key\": \"%4095[^\"]\", \"vec\": %d, \"unroll\": %d, \"bpc\": %d, "
+                            "\"rb\": %d, \"pe\": %d}",
+                            key, &s.vec_max, &s.unroll, &s.blocks_per_cu, &s.rb_max, &s.pe_target);
+        if (n != 6)
+            continue;  // corrupt or foreign line: ignored
+        if ((s.vec_max != 1 && s.vec_max != 2 && s.vec_max != 4) ||
+            (s.unroll != 2 && s.unroll != 4 && s.unroll != 8) || s.blocks_per_cu < 1 ||
+            s.blocks_per_cu > 32 || s.rb_max < 1 || s.rb_max > RB_MAX || s.pe_target < 64 ||
+            s.pe_target > (1 << 24))
+            continue;
+        g_sched[key] = s;
+    }
+    std::fclose(f);
+}
+
+void ensure_loaded()
+{
+    if (g_loaded)
+        return;
+    g_loaded = true;
+    const char *p = std::getenv("TRIOT_TUNE_CACHE");
+    if (p && *p)
+        load_cache_file(p);
+}
+
+Sched sched_for(const Request &r)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    ensure_loaded();
+    auto it = g_sched.find(sched_key(r));
+    return it == g_sched.end() ? Sched() : it->second;
+}
+
+triot_status to_status(hipError_t e)
+{
+    return e == hipSuccess ? TRIOT_OK : TRIOT_E_DEVICE;
+}
+
+triot_status run_request(const Request &r, const Sched &s, void *out, void *workspace,
+                         size_t workspace_bytes, hipStream_t stream)
+{
+    if (r.npoints == 0)
+        return TRIOT_OK;
+    const int cus = device_cus();
+    if (is_segment_op(r.op)) {
+        SegLaunch L;
+        triot_status st = plan_segment(r, cus, &L);
+        if (st != TRIOT_OK)
+            return st;
+        if (r.op == TRIOT_OP_MOMENTS) {
+            if (!out)
+                return TRIOT_E_INVALID;
+            if (!workspace || workspace_bytes < segment_workspace_bytes(L))
+                return TRIOT_E_WORKSPACE;
+            L.plan.out32 = (uint64_t)(uintptr_t)out;
+            L.plan.out64 = r.params
+                               ? (uint64_t)(uintptr_t)((const triot_moments_params *)r.params)->out64
+                               : 0;
+            L.plan.ws = (uint64_t)(uintptr_t)workspace;
+            return to_status(launch_moments(L, stream));
+        }
+        const triot_moments_adj_params *p = (const triot_moments_adj_params *)r.params;
+        L.plan.out64 = (uint64_t)(uintptr_t)p->mom;
+        L.plan.gmom = (uint64_t)(uintptr_t)p->gmom;
+        return to_status(launch_moments_adj(L, stream));
+    }
+    CoLaunch L;
+    triot_status st = plan_coiter(r, s, cus, &L);
+    if (st != TRIOT_OK)
+        return st;
+    return to_status(launch_coiter(co_op_of(r.op), L, stream));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------
+
+extern "C" triot_status triot_apply(triot_op op, int n_tensors, int d, const int64_t *shapes,
+                                    const int64_t *counter_shape, void *const *tensors,
+                                    const int64_t *bases, const void *params, void *out,
+                                    void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    Request r;
+    triot_status st = validate(op, n_tensors, d, shapes, counter_shape, tensors, bases, params, &r);
+    if (st != TRIOT_OK)
+        return st;
+    Sched s = is_segment_op(op) ? Sched() : sched_for(r);
+    return run_request(r, s, out, workspace, workspace_bytes, stream);
+}
+
+extern "C" size_t triot_workspace_size(triot_op op, int n_tensors, int d, const int64_t *shapes,
+                                       const int64_t *counter_shape)
+{
+    if (op != TRIOT_OP_MOMENTS)
+        return 0;
+    void *dummy[TRIOT_MAX_TENSORS];
+    for (int k = 0; k < TRIOT_MAX_TENSORS; ++k)
+        dummy[k] = (void *)(uintptr_t)256;
+    Request r;
+    if (validate(op, n_tensors, d, shapes, counter_shape, dummy, nullptr, nullptr, &r) != TRIOT_OK)
+        return 0;
+    // The covariance tier is the larger one; size for it.
+    triot_moments_params mp;
+    mp.flags = TRIOT_MOMENTS_FIRST | TRIOT_MOMENTS_COV;
+    mp.out64 = nullptr;
+    r.params = &mp;
+    SegLaunch L;
+    if (plan_segment(r, device_cus(), &L) != TRIOT_OK) {
+        mp.flags = TRIOT_MOMENTS_FIRST;
+        if (plan_segment(r, device_cus(), &L) != TRIOT_OK)
+            return 0;
+    }
+    return segment_workspace_bytes(L);
+}
+
+extern "C" const char *triot_status_string(triot_status s)
+{
+    switch (s) {
+    case TRIOT_OK: return "ok";
+    case TRIOT_E_INVALID: return "invalid argument";
+    case TRIOT_E_DIM: return "dimension out of range";
+    case TRIOT_E_BOUNDS: return "counter exceeds an operand window";
+    case TRIOT_E_ALIAS: return "output overlaps another operand";
+    case TRIOT_E_OVERFLOW: return "size or offset overflows int64";
+    case TRIOT_E_WORKSPACE: return "workspace missing or too small";
+    case TRIOT_E_DEVICE: return "HIP device error";
+    case TRIOT_E_UNSUPPORTED: return "outside this build's limits";
+    }
+    return "unknown status";
+}
+
+extern "C" triot_status triot_divmod_magic(uint32_t c, uint32_t *m, uint32_t *s)
+{
+    AxisDiv a;
+    if (!m || !s || !magic_for(c, &a))
+        return TRIOT_E_INVALID;
+    *m = a.m;
+    *s = a.s;
+    return TRIOT_OK;
+}
+
+extern "C" triot_status triot_plan_describe(triot_op op, int n_tensors, int d, const int64_t *shapes,
+                                            const int64_t *counter_shape, void *const *tensors,
+                                            const int64_t *bases, const void *params,
+                                            triot_plan_info *info)
+{
+    if (!info)
+        return TRIOT_E_INVALID;
+    std::memset(info, 0, sizeof(*info));
+    Request r;
+    triot_status st = validate(op, n_tensors, d, shapes, counter_shape, tensors, bases, params, &r);
+    if (st != TRIOT_OK)
+        return st;
+    if (r.npoints == 0)
+        return TRIOT_OK;
+    const int cus = device_cus();
+    if (is_segment_op(op)) {
+        SegLaunch L;
+        st = plan_segment(r, cus, &L);
+        if (st != TRIOT_OK)
+            return st;
+        info->kernel = 1;
+        info->dims = (int)L.plan.D;
+        for (int i = 0; i < (int)L.plan.D - 1; ++i)
+            info->extents[i] = L.plan.ax[i].c;
+        info->extents[L.plan.D - 1] = L.plan.L;
+        info->vec = 1;
+        info->units = (int64_t)L.plan.ntiles;
+        info->blocks = L.blocks;
+        info->threads = NT;
+        info->unroll = 1;
+        return TRIOT_OK;
+    }
+    CoLaunch L;
+    st = plan_coiter(r, sched_for(r), cus, &L);
+    if (st != TRIOT_OK)
+        return st;
+    const CoPlan &P = L.plan;
+    info->kernel = 0;
+    info->dims = (int)P.D;
+    for (int i = 0; i < (int)P.D - 1; ++i)
+        info->extents[i] = P.ax[i].c;
+    info->extents[P.D - 1] = (int64_t)P.L * P.vec;
+    info->vec = (int)P.vec;
+    info->high_axes = (int)P.nhigh;
+    info->low_axes = (int)P.nlow;
+    info->box_rows = P.RB;
+    info->units = P.nunits;
+    info->blocks = L.blocks;
+    info->threads = NT;
+    info->unroll = L.unroll;
+    return TRIOT_OK;
+}
+
+// ---- autotuner ---------------------------------------------------------
+
+extern "C" void triot_tune_reset(void)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    g_sched.clear();
+    g_loaded = true;  // an explicit reset also forgets the environment's cache
+}
+
+extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const int64_t *shapes,
+                                       const int64_t *counter_shape, void *const *tensors,
+                                       const int64_t *bases, const void *params, void *out,
+                                       void *workspace, size_t workspace_bytes, hipStream_t stream,
+                                       const char *cache_path)
+{
+    Request r;
+    triot_status st = validate(op, n_tensors, d, shapes, counter_shape, tensors, bases, params, &r);
+    if (st != TRIOT_OK)
+        return st;
+    if (r.npoints == 0 || is_segment_op(op))
+        return TRIOT_OK;  // nothing to choose: the row kernels have one schedule
+    hipEvent_t ev0, ev1;
+    if (hipEventCreate(&ev0) != hipSuccess)
+        return TRIOT_E_DEVICE;
+    if (hipEventCreate(&ev1) != hipSuccess) {
+        (void)hipEventDestroy(ev0);
+        return TRIOT_E_DEVICE;
+    }
+    auto time_it = [&](const Sched &s, float *ms) -> triot_status {
+        triot_status t = run_request(r, s, out, workspace, workspace_bytes, stream);  // warm-up
+        if (t != TRIOT_OK)
+            return t;
+        const int reps = 5;
+        if (hipEventRecord(ev0, stream) != hipSuccess)
+            return TRIOT_E_DEVICE;
+        for (int i = 0; i < reps; ++i) {
+            t = run_request(r, s, out, workspace, workspace_bytes, stream);
+            if (t != TRIOT_OK)
+                return t;
+        }
+        if (hipEventRecord(ev1, stream) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess)
+            return TRIOT_E_DEVICE;
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, ev0, ev1) != hipSuccess)
+            return TRIOT_E_DEVICE;
+        *ms = e / reps;
+        return TRIOT_OK;
+    };
+    Sched best;
+    float best_ms = 0.f;
+    st = time_it(best, &best_ms);
+    // Coordinate descent over the knobs, each from the best so far.
+    const int vecs[] = {4, 2, 1};
+    const int unrolls[] = {2, 4, 8};
+    const int bpcs[] = {2, 4, 8, 16};
+    const int rbs[] = {32, 64, 128, 256};
+    const int pes[] = {2048, 4096, 8192, 16384, 32768};
+    for (int pass = 0; pass < 2 && st == TRIOT_OK; ++pass) {
+        auto sweep = [&](int Sched::*field, const int *vals, int nvals) {
+            for (int i = 0; i < nvals && st == TRIOT_OK; ++i) {
+                Sched s = best;
+                if (s.*field == vals[i])
+                    continue;
+                s.*field = vals[i];
+                float ms;
+                triot_status t = time_it(s, &ms);
+                if (t == TRIOT_E_UNSUPPORTED)
+                    continue;
+                if (t != TRIOT_OK) {
+                    st = t;
+                    return;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = s;
+                }
+            }
+        };
+        sweep(&Sched::vec_max, vecs, 3);
+        sweep(&Sched::unroll, unrolls, 3);
+        sweep(&Sched::blocks_per_cu, bpcs, 4);
+        sweep(&Sched::rb_max, rbs, 4);
+        sweep(&Sched::pe_target, pes, 5);
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (st != TRIOT_OK)
+        return st;
+    const std::string key = sched_key(r);
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        ensure_loaded();
+        g_sched[key] = best;
+    }
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "a");
+        if (f) {
+            std::fprintf(f,
+                         "{\"key\": \"%s\", \"vec\": %d, \"unroll\": %d, \"bpc\": %d, \"rb\": %d, "
+                         "\"pe\": %d}\n",
+                         key.c_str(), best.vec_max, best.unroll, best.blocks_per_cu, best.rb_max,
+                         best.pe_target);
+            std::fclose(f);
+        }
+    }
+    return TRIOT_OK;
+}
+
+// ---- batched form --------------------------------------------------------
+
+struct triot_batch {
+    std::vector<int64_t> sig;     // what the captured graph was built for
+    CoPlan *d_plans = nullptr;
+    uint32_t *d_ustart = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    int device = -1;
+    int blocks = 0;
+    int64_t units = 0;
+    int replayed = 0;
+};
+
+static void batch_release(triot_batch *b)
+{
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    if (b->d_plans)
+        (void)hipFree(b->d_plans);
+    if (b->d_ustart)
+        (void)hipFree(b->d_ustart);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->d_plans = nullptr;
+    b->d_ustart = nullptr;
+    b->sig.clear();
+}
+
+extern "C" triot_status triot_batch_create(triot_batch **handle)
+{
+    if (!handle)
+        return TRIOT_E_INVALID;
+    *handle = new (std::nothrow) triot_batch();
+    return *handle ? TRIOT_OK : TRIOT_E_INVALID;
+}
+
+extern "C" void triot_batch_destroy(triot_batch *handle)
+{
+    if (!handle)
+        return;
+    batch_release(handle);
+    if (handle->cap)
+        (void)hipStreamDestroy(handle->cap);
+    delete handle;
+}
+
+extern "C" triot_status triot_batch_info(const triot_batch *handle, int64_t *n_units, int *n_blocks,
+                                         int *replayed)
+{
+    if (!handle)
+        return TRIOT_E_INVALID;
+    if (n_units)
+        *n_units = handle->units;
+    if (n_blocks)
+        *n_blocks = handle->blocks;
+    if (replayed)
+        *replayed = handle->replayed;
+    return TRIOT_OK;
+}
+
+extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const triot_item *items,
+                                            const void *params, triot_batch *handle,
+                                            hipStream_t stream)
+{
+    if (!handle || n_items < 0 || (n_items > 0 && !items))
+        return TRIOT_E_INVALID;
+    if (op != TRIOT_OP_COPY && op != TRIOT_OP_EMBED_FILL && op != TRIOT_OP_MUL_ACC &&
+        op != TRIOT_OP_MUL)
+        return TRIOT_E_UNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return TRIOT_E_DEVICE;
+
+    // Validate every item and build the signature of the batch.
+    std::vector<Request> reqs((size_t)n_items);
+    std::vector<int64_t> sig;
+    sig.reserve((size_t)n_items * 16 + 4);
+    sig.push_back((int64_t)op);
+    sig.push_back(n_items);
+    sig.push_back(dev);
+    sig.push_back(params && (op == TRIOT_OP_COPY || op == TRIOT_OP_EMBED_FILL)
+                      ? ((const triot_copy_params *)params)->elem_bytes
+                      : 4);
+    for (int i = 0; i < n_items; ++i) {
+        const triot_item &it = items[i];
+        triot_status st = validate(op, it.n_tensors, it.d, it.shapes, it.counter_shape, it.tensors,
+                                   it.bases, params, &reqs[(size_t)i]);
+        if (st != TRIOT_OK)
+            return st;
+        const Request &r = reqs[(size_t)i];
+        sig.push_back(r.d);
+        sig.push_back(r.n);
+        for (int k = 0; k < r.n; ++k) {
+            for (int a = 0; a < r.d; ++a)
+                sig.push_back(r.shape[k][a]);
+            sig.push_back(r.base[k]);
+            sig.push_back((int64_t)(uintptr_t)r.ptr[k]);
+        }
+        for (int a = 0; a < r.d; ++a)
+            sig.push_back(r.counter[a]);
+    }
+
+    if (handle->exec && handle->device == dev && handle->sig == sig) {
+        handle->replayed = 1;
+        return to_status(hipGraphLaunch(handle->exec, stream));
+    }
+
+    // Plan every item (4-byte lanes keep one code path for any alignment).
+    batch_release(handle);
+    handle->replayed = 0;
+    Sched s;
+    s.vec_max = 1;
+    s.pe_target = 4096;
+    const int cus = device_cus();
+    std::vector<CoPlan> plans;
+    std::vector<uint32_t> ustart;
+    plans.reserve((size_t)n_items);
+    ustart.push_back(0);
+    uint64_t total = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const Request &r = reqs[(size_t)i];
+        if (r.npoints == 0)
+            continue;
+        CoLaunch L;
+        triot_status st = plan_coiter(r, s, cus, &L);
+        if (st != TRIOT_OK)
+            return st;
+        plans.push_back(L.plan);
+        total += L.plan.nunits;
+        if (total >= (uint64_t(1) << 32))
+            return TRIOT_E_UNSUPPORTED;
+        ustart.push_back((uint32_t)total);
+    }
+    handle->units = (int64_t)total;
+    handle->device = dev;
+    if (total == 0) {
+        handle->blocks = 0;
+        return TRIOT_OK;
+    }
+    int blocks = (int)std::min<uint64_t>(total, (uint64_t)cus * 4);
+    if (blocks > 8)
+        blocks = (blocks + 7) / 8 * 8;
+    handle->blocks = blocks;
+
+    if (hipMalloc((void **)&handle->d_plans, plans.size() * sizeof(CoPlan)) != hipSuccess ||
+        hipMalloc((void **)&handle->d_ustart, ustart.size() * sizeof(uint32_t)) != hipSuccess) {
+        batch_release(handle);
+        return TRIOT_E_DEVICE;
+    }
+    if (hipMemcpy(handle->d_plans, plans.data(), plans.size() * sizeof(CoPlan),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(handle->d_ustart, ustart.data(), ustart.size() * sizeof(uint32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        batch_release(handle);
+        return TRIOT_E_DEVICE;
+    }
+    if (!handle->cap &&
+        hipStreamCreateWithFlags(&handle->cap, hipStreamNonBlocking) != hipSuccess) {
+        handle->cap = nullptr;
+        batch_release(handle);
+        return TRIOT_E_DEVICE;
+    }
+    // Capture the single persistent launch on the library's own stream
+    // (capture is not allowed on the null stream), then replay it on the
+    // caller's.
+    const uint32_t nitems = (uint32_t)plans.size();
+    if (hipStreamBeginCapture(handle->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        batch_release(handle);
+        return TRIOT_E_DEVICE;
+    }
+    hipError_t le = launch_batched(co_op_of(op), handle->d_plans, handle->d_ustart, nitems,
+                                   (uint32_t)total, blocks, handle->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(handle->cap, &graph);
+    if (le != hipSuccess || ce != hipSuccess || !graph) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        batch_release(handle);
+        return TRIOT_E_DEVICE;
+    }
+    handle->graph = graph;
+    if (hipGraphInstantiate(&handle->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        handle->exec = nullptr;
+        batch_release(handle);
+        return TRIOT_E_DEVICE;
+    }
+    handle->sig = std::move(sig);
+    return to_status(hipGraphLaunch(handle->exec, stream));
+}

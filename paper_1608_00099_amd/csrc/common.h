@@ -1,0 +1,112 @@
+// Internal plan layouts shared by the host planner and the gfx950 kernels.
+//
+// A plan is everything a kernel needs to co-iterate, passed by value as the
+// kernel argument (the kernel-argument segment is constant memory read
+// through the scalar cache), or, for batches, stored in device memory.
+#pragma once
+
+#include <stdint.h>
+
+#include "triot.h"
+
+namespace triot {
+
+constexpr int MAXD = TRIOT_MAX_D;
+constexpr int MAXT = TRIOT_MAX_TENSORS;
+constexpr uint32_t NOBOUND = 0xFFFFFFFFu;
+constexpr int NT = 256;           // threads per workgroup (4 wave64)
+constexpr int RB_MAX = 256;       // LDS row-table capacity (rows per box)
+constexpr int SEG_MAX = 32;       // per-thread segment length of the row kernels
+constexpr int MOM_TERMS_MAX = 1 + MAXD + 8 * 9 / 2;  // covariance limited to 8 axes
+
+// Internal op ids of the element-wise family (kernel template argument).
+enum CoOp : int {
+    CO_COPY = 0,
+    CO_FILL = 1,
+    CO_MUL_ACC = 2,
+    CO_MUL = 3,
+    CO_MUL_ADJ = 4,
+    CO_INDEX = 5,
+};
+
+// Division of a 32-bit n by an invariant divisor c >= 2 (Granlund &
+// Montgomery, PLDI 1994, round-up multiplier with add-back):
+//   h = mulhi(n, m);  q = (h + ((n - h) >> 1)) >> s
+// with l = ceil(log2 c), m = floor(2^32 (2^l - c) / c) + 1, s = l - 1.
+struct AxisDiv {
+    uint32_t c, m, s, pad;
+};
+
+// ---------------------------------------------------------------------
+// Element-wise co-iteration plan (one lane per counter element).
+//
+// The planned counter has D axes (extent-1 axes dropped, adjacent axes
+// merged where every operand is contiguous across them): D-1 outer axes
+// and one inner axis of extent L, all in units of `vec` 4-byte words.
+// The outer axes split into `nhigh` high axes and `nlow` low axes.  A
+// *box* is one value of the high axes: RB = prod(low extents) rows of L
+// elements.  Every workgroup tabulates, once, the offset of each box row
+// relative to the box start (low axes only, so the table is the same for
+// every box); a work unit is one box part of at most PE elements, whose
+// high tuple is decoded once, uniformly, by magic division.
+struct CoPlan {
+    uint32_t D, n, nhigh, nlow;
+    uint32_t L;          // inner extent
+    uint32_t Lm;         // ceil(2^32 / L): e / L == mulhi(e, Lm) for e < 2^32 / L (RB > 1)
+    uint32_t RB;         // rows per box
+    uint32_t BE;         // elements per box (RB * L)
+    uint32_t parts;      // units per box
+    uint32_t PE;         // elements per unit
+    AxisDiv partdiv;     // unit -> (box, part); c == 1 means parts == 1
+    uint32_t nunits;     // boxes * parts
+    uint32_t predmask;   // bit k: operand k only where t lies inside its window
+    uint32_t esz;        // bytes per vector element (4 * vec)
+    uint32_t vec;
+    uint32_t unit;       // 1 when every inner stride is 1
+    uint32_t pad0;
+    AxisDiv ax[MAXD];                 // outer axes, outermost first
+    int64_t stride[MAXT][MAXD];       // outer strides per operand (vector units)
+    uint32_t bound[MAXT][MAXD];       // window extent per outer axis (NOBOUND = unchecked)
+    uint32_t ibound[MAXT];            // window extent on the inner axis
+    uint32_t istride[MAXT];           // inner stride (vector units)
+    int64_t base[MAXT];               // vector units
+    uint64_t ptr[MAXT];               // device byte addresses
+    uint64_t npoints;                 // counter points (INDEX output leading dimension)
+};
+
+// ---------------------------------------------------------------------
+// Row-segment plan (moments and their adjoint: one thread per segment).
+//
+// Logical axes only (extent-1 axes dropped, no merging, the tuple is read):
+// D axes, D-1 outer and the inner one of extent L.  Each row splits into G
+// segments of at most S elements; a thread folds one segment at a time.
+// When every operand is contiguous over the counter (`full`), a workgroup
+// stages its NT consecutive segments through LDS with coalesced accesses.
+struct SegPlan {
+    uint32_t D, n;
+    uint32_t d_orig;
+    uint32_t L, S, G;
+    AxisDiv gdiv;             // segment -> (row, part of row); c == 1 means G == 1
+    uint32_t rows;            // counter rows (< 2^32)
+    uint32_t full;
+    uint32_t flags;           // TRIOT_MOMENTS_* bits
+    uint32_t nblocks;         // grid size (moments: number of partials)
+    uint32_t nterms;          // accumulated terms: 1 + D (+ D(D+1)/2)
+    uint64_t nseg;            // rows * G
+    uint64_t ntiles;          // ceil(nseg / NT)
+    AxisDiv ax[MAXD];         // outer axes 0..D-2
+    double center[MAXD];      // shift (c-1)/2 per kept axis
+    uint32_t orig[MAXD];      // original axis of kept axis i
+    int64_t stride[4][MAXD];  // element strides per operand (inner at D-1)
+    int64_t base[4];
+    uint64_t ptr[4];
+    uint64_t out32;           // MOMENTS: float results
+    uint64_t out64;           // MOMENTS: optional double results; ADJ: moments in
+    uint64_t gmom;            // ADJ: float partials
+    uint64_t ws;              // MOMENTS: partials + ticket
+};
+
+// Host-side helpers (plan.cpp).
+bool magic_for(uint32_t c, AxisDiv *out);
+
+}  // namespace triot

@@ -1,0 +1,455 @@
+// Element-wise co-iteration kernels for gfx950 (CDNA4, wave64).
+//
+// One lane per counter element, elements in row-major counter order, so
+// that consecutive lanes touch consecutive addresses along the innermost
+// (collapsed) axis of every operand.  The flat -> tuple decode of the paper
+// (Section 1, reindexing by remainder and quotient) is split in three:
+//   - the high axes of a work unit are decoded once, uniformly (scalar
+//     registers), by magic-number division, giving every operand's 64-bit
+//     box base;
+//   - the low axes are decoded once per workgroup into an LDS table of
+//     32-bit row offsets, identical for every box;
+//   - per element only row = e / L (one mulhi) and the table lookup remain.
+// Offsets are the row-major (Horner) sums of Section 1.  Windows (slices
+// with a bias, Section 4) enter through the operand bases, partial reads
+// (zero-filled embedding, adjoints) through per-axis window bounds.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "launch.h"
+
+namespace triot {
+
+__device__ __forceinline__ uint32_t div_u32(uint32_t n, const AxisDiv &a)
+{
+    uint32_t h = __umulhi(n, a.m);
+    return (h + ((n - h) >> 1)) >> a.s;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2); consecutive logical blocks should share an XCD so that neighbouring
+// work units (and the partially written cache lines between them) meet in
+// one L2.
+__device__ __forceinline__ uint32_t logical_block()
+{
+    uint32_t g = gridDim.x, b = blockIdx.x;
+    if ((g & 7u) == 0)
+        return (b & 7u) * (g >> 3) + (b >> 3);
+    return b;
+}
+
+template <int V> struct Vec;
+template <> struct Vec<1> {
+    typedef uint32_t U;
+    typedef float F;
+};
+template <> struct Vec<2> {
+    typedef uint32_t U __attribute__((ext_vector_type(2)));
+    typedef float F __attribute__((ext_vector_type(2)));
+};
+template <> struct Vec<4> {
+    typedef uint32_t U __attribute__((ext_vector_type(4)));
+    typedef float F __attribute__((ext_vector_type(4)));
+};
+
+struct RowTable {
+    uint32_t off[MAXT][RB_MAX];   // pre-adjusted byte offsets of each box row
+    uint32_t mask[RB_MAX];        // bit k: the row lies inside operand k's window
+};
+
+// Tabulate the box rows: decode each row over the low axes and store, per
+// operand, (row offset - row * L * istride) * esz so that an element e of
+// the box sits at table[row] + e * istride * esz bytes from the box base.
+__device__ void fill_table(const CoPlan &P, RowTable &T)
+{
+    const uint32_t n = P.n, nhigh = P.nhigh, nlow = P.nlow;
+    for (uint32_t r = threadIdx.x; r < P.RB; r += NT) {
+        uint32_t rel[MAXT];
+#pragma unroll
+        for (int k = 0; k < MAXT; ++k)
+            rel[k] = 0;
+        uint32_t mask = 0xFFFFFFFFu;
+        uint32_t q = r;
+        for (int j = (int)(nhigh + nlow) - 1; j >= (int)nhigh; --j) {
+            const AxisDiv a = P.ax[j];
+            uint32_t qq = div_u32(q, a);
+            uint32_t t = q - qq * a.c;
+            q = qq;
+#pragma unroll
+            for (int k = 0; k < MAXT; ++k) {
+                if (k < (int)n) {
+                    rel[k] += t * (uint32_t)P.stride[k][j];
+                    if (t >= P.bound[k][j])
+                        mask &= ~(1u << k);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MAXT; ++k)
+            if (k < (int)n)
+                T.off[k][r] = (rel[k] - r * P.L * P.istride[k]) * P.esz;
+        T.mask[r] = mask;
+    }
+}
+
+template <int OP> struct OpInfo;
+template <> struct OpInfo<CO_COPY> { static constexpr int N = 2; static constexpr bool PRED = false; };
+template <> struct OpInfo<CO_FILL> { static constexpr int N = 2; static constexpr bool PRED = true; };
+template <> struct OpInfo<CO_MUL_ACC> { static constexpr int N = 3; static constexpr bool PRED = false; };
+template <> struct OpInfo<CO_MUL> { static constexpr int N = 3; static constexpr bool PRED = false; };
+template <> struct OpInfo<CO_MUL_ADJ> { static constexpr int N = 5; static constexpr bool PRED = true; };
+template <> struct OpInfo<CO_INDEX> { static constexpr int N = MAXT; static constexpr bool PRED = false; };
+
+// Process one work unit (a part of one box).
+template <int OP, int V, int U, bool ROWS1, bool UNIT>
+__device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const RowTable &T)
+{
+    typedef typename Vec<V>::U VU;
+    typedef typename Vec<V>::F VF;
+    constexpr int N = OpInfo<OP>::N;
+    const uint32_t n = (OP == CO_INDEX) ? P.n : (uint32_t)N;
+
+    // ---- uniform: unit -> (box, part) -> high tuple -> box bases ----
+    uint32_t box, part;
+    if (P.partdiv.c == 1) {
+        box = unit;
+        part = 0;
+    } else {
+        box = div_u32(unit, P.partdiv);
+        part = unit - box * P.parts;
+    }
+    int64_t bb[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        bb[k] = (k < (int)n) ? P.base[k] : 0;
+    uint32_t himask = 0xFFFFFFFFu;
+    {
+        uint32_t q = box;
+        for (int i = (int)P.nhigh - 1; i >= 0; --i) {
+            uint32_t t;
+            if (i == 0) {
+                t = q;
+            } else {
+                const AxisDiv a = P.ax[i];
+                uint32_t qq = div_u32(q, a);
+                t = q - qq * a.c;
+                q = qq;
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                if (k < (int)n) {
+                    bb[k] += (int64_t)t * P.stride[k][i];
+                    if (OpInfo<OP>::PRED && t >= P.bound[k][i])
+                        himask &= ~(1u << k);
+                }
+            }
+        }
+    }
+    const uint32_t e0 = part * P.PE;
+    const uint32_t e1 = min(e0 + P.PE, P.BE);
+    if (ROWS1) {
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (k < (int)n)
+                bb[k] += (int64_t)e0 * P.istride[k];
+    }
+    const uint32_t esz = P.esz;
+    char *bp[N];
+    uint32_t isb[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        bp[k] = (char *)(uintptr_t)(P.ptr[k < (int)n ? k : 0]) + bb[k] * (int64_t)esz;
+        isb[k] = UNIT ? esz : P.istride[k < (int)n ? k : 0] * esz;
+    }
+
+    // ---- per element ----
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += NT * U) {
+        uint32_t ev[U];
+        bool valid[U];
+        uint32_t off[N][U];
+        uint32_t pm[U];
+        uint32_t jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint32_t x = e + (uint32_t)u * NT;
+            valid[u] = x < e1;
+            x = valid[u] ? x : e0;
+            ev[u] = x;
+            uint32_t row, j;
+            if (ROWS1) {
+                row = 0;
+                j = x;
+            } else {
+                row = __umulhi(x, P.Lm);
+                j = x - row * P.L;
+            }
+            jj[u] = j;
+            pm[u] = 0xFFFFFFFFu;
+            if (OpInfo<OP>::PRED) {
+                uint32_t m = himask & (ROWS1 ? 0xFFFFFFFFu : T.mask[row]);
+#pragma unroll
+                for (int k = 0; k < N; ++k)
+                    if (j >= P.ibound[k])
+                        m &= ~(1u << k);
+                pm[u] = m;
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                if (k < (int)n) {
+                    uint32_t rel = ROWS1 ? 0u : T.off[k][row];
+                    uint32_t xe = ROWS1 ? (x - e0) : x;
+                    off[k][u] = rel + xe * isb[k];
+                }
+            }
+        }
+
+        if constexpr (OP == CO_COPY) {
+            VU v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u])
+                    v[u] = *(const VU *)(bp[1] + off[1][u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u])
+                    *(VU *)(bp[0] + off[0][u]) = v[u];
+        } else if constexpr (OP == CO_FILL) {
+            VU v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                v[u] = (VU)0u;
+                if (valid[u] && (pm[u] & 2u))
+                    v[u] = *(const VU *)(bp[1] + off[1][u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u])
+                    *(VU *)(bp[0] + off[0][u]) = v[u];
+        } else if constexpr (OP == CO_MUL_ACC) {
+            VF x[U], y[U], z[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u]) {
+                    x[u] = *(const VF *)(bp[0] + off[0][u]);
+                    y[u] = *(const VF *)(bp[1] + off[1][u]);
+                    z[u] = *(const VF *)(bp[2] + off[2][u]);
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u]) {
+                    VF prod = y[u] * z[u];       // rounded once (no contraction)
+                    *(VF *)(bp[0] + off[0][u]) = x[u] + prod;
+                }
+        } else if constexpr (OP == CO_MUL) {
+            VF a[U], b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u]) {
+                    a[u] = *(const VF *)(bp[1] + off[1][u]);
+                    b[u] = *(const VF *)(bp[2] + off[2][u]);
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u])
+                    *(VF *)(bp[0] + off[0][u]) = a[u] * b[u];
+        } else if constexpr (OP == CO_MUL_ADJ) {
+            // operands: 0 ga, 1 gb, 2 gout, 3 a, 4 b
+            VF g[U], a[U], b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                g[u] = (VF)0.0f;
+                a[u] = (VF)0.0f;
+                b[u] = (VF)0.0f;
+                const bool inI = valid[u] && (pm[u] & 4u);
+                if (inI) {
+                    g[u] = *(const VF *)(bp[2] + off[2][u]);
+                    if (pm[u] & 2u)
+                        a[u] = *(const VF *)(bp[3] + off[3][u]);
+                    if (pm[u] & 1u)
+                        b[u] = *(const VF *)(bp[4] + off[4][u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!valid[u])
+                    continue;
+                const bool inI = (pm[u] & 4u) != 0;
+                if (pm[u] & 1u)
+                    *(VF *)(bp[0] + off[0][u]) = inI ? g[u] * b[u] : (VF)0.0f;
+                if (pm[u] & 2u)
+                    *(VF *)(bp[1] + off[1][u]) = inI ? g[u] * a[u] : (VF)0.0f;
+            }
+        } else if constexpr (OP == CO_INDEX) {
+            // Element offsets (base included) of every operand, row-major
+            // counter index f = box * BE + e.
+            int64_t *out = (int64_t *)(uintptr_t)P.ptr[0];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!valid[u])
+                    continue;
+                uint64_t f = (uint64_t)box * P.BE + ev[u];
+#pragma unroll
+                for (int k = 0; k < N; ++k)
+                    if (k < (int)n)
+                        out[(uint64_t)k * P.npoints + f] = bb[k] + (int64_t)(off[k][u] >> 2);  // esz == 4
+            }
+        }
+        (void)jj;
+    }
+}
+
+template <int OP, int V, int U, bool ROWS1, bool UNIT>
+__global__ __launch_bounds__(NT) void coiter_kernel(const CoPlan P)
+{
+    __shared__ RowTable T;
+    if (!ROWS1) {
+        fill_table(P, T);
+        __syncthreads();
+    }
+    const uint32_t lb = logical_block();
+    const uint32_t g = gridDim.x;
+    const uint32_t u0 = (uint32_t)(((uint64_t)lb * P.nunits) / g);
+    const uint32_t u1 = (uint32_t)(((uint64_t)(lb + 1) * P.nunits) / g);
+    for (uint32_t u = u0; u < u1; ++u)
+        run_unit<OP, V, U, ROWS1, UNIT>(P, u, T);
+}
+
+// ---------------------------------------------------------------------
+// Batched persistent kernel: one launch over a device table of item plans.
+// Work units of all items are numbered consecutively (ustart holds each
+// item's first unit); every workgroup walks a contiguous range of units and
+// re-tabulates its box rows whenever the range enters a new item.
+// ---------------------------------------------------------------------
+template <int OP, int U>
+__global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ plans,
+                                                     const uint32_t *__restrict__ ustart,
+                                                     uint32_t nitems, uint32_t total)
+{
+    __shared__ RowTable T;
+    const uint32_t lb = logical_block();
+    const uint32_t g = gridDim.x;
+    const uint32_t u0 = (uint32_t)(((uint64_t)lb * total) / g);
+    const uint32_t u1 = (uint32_t)(((uint64_t)(lb + 1) * total) / g);
+    if (u0 >= u1)
+        return;
+    uint32_t lo = 0, hi = nitems;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (ustart[mid] <= u0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    uint32_t item = lo;
+    uint32_t cur = 0xFFFFFFFFu;
+    for (uint32_t u = u0; u < u1; ++u) {
+        while (u >= ustart[item + 1])
+            ++item;
+        const CoPlan &P = plans[item];
+        const bool rows1 = P.RB == 1;
+        if (item != cur) {
+            __syncthreads();
+            if (!rows1)
+                fill_table(P, T);
+            __syncthreads();
+            cur = item;
+        }
+        const uint32_t lu = u - ustart[item];
+        if (rows1) {
+            if (P.unit)
+                run_unit<OP, 1, U, true, true>(P, lu, T);
+            else
+                run_unit<OP, 1, U, true, false>(P, lu, T);
+        } else {
+            if (P.unit)
+                run_unit<OP, 1, U, false, true>(P, lu, T);
+            else
+                run_unit<OP, 1, U, false, false>(P, lu, T);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------
+
+template <int OP, int V, int U, bool ROWS1, bool UNIT>
+static hipError_t go(const CoLaunch &L, hipStream_t st)
+{
+    hipLaunchKernelGGL((coiter_kernel<OP, V, U, ROWS1, UNIT>), dim3(L.blocks), dim3(NT), 0, st,
+                       L.plan);
+    return hipGetLastError();
+}
+
+template <int OP, int V, int U>
+static hipError_t pick_rows(const CoLaunch &L, hipStream_t st)
+{
+    if (L.rows1)
+        return L.unit ? go<OP, V, U, true, true>(L, st) : go<OP, V, U, true, false>(L, st);
+    return L.unit ? go<OP, V, U, false, true>(L, st) : go<OP, V, U, false, false>(L, st);
+}
+
+template <int OP, int U>
+static hipError_t pick_vec(const CoLaunch &L, hipStream_t st)
+{
+    if constexpr (OP == CO_INDEX) {
+        return pick_rows<OP, 1, U>(L, st);
+    } else {
+        switch (L.plan.vec) {
+        case 4: return pick_rows<OP, 4, U>(L, st);
+        case 2: return pick_rows<OP, 2, U>(L, st);
+        default: return pick_rows<OP, 1, U>(L, st);
+        }
+    }
+}
+
+template <int OP>
+static hipError_t pick_unroll(const CoLaunch &L, hipStream_t st)
+{
+    if (L.unroll >= 8)
+        return pick_vec<OP, 8>(L, st);
+    if (L.unroll <= 2)
+        return pick_vec<OP, 2>(L, st);
+    return pick_vec<OP, 4>(L, st);
+}
+
+hipError_t launch_coiter(int co_op, const CoLaunch &L, hipStream_t st)
+{
+    switch (co_op) {
+    case CO_COPY: return pick_unroll<CO_COPY>(L, st);
+    case CO_FILL: return pick_unroll<CO_FILL>(L, st);
+    case CO_MUL_ACC: return pick_unroll<CO_MUL_ACC>(L, st);
+    case CO_MUL: return pick_unroll<CO_MUL>(L, st);
+    case CO_MUL_ADJ: return pick_unroll<CO_MUL_ADJ>(L, st);
+    case CO_INDEX: return pick_vec<CO_INDEX, 4>(L, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batched(int co_op, const CoPlan *plans, const uint32_t *ustart, uint32_t nitems,
+                          uint32_t total, int blocks, hipStream_t st)
+{
+    switch (co_op) {
+    case CO_COPY:
+        hipLaunchKernelGGL((batched_kernel<CO_COPY, 4>), dim3(blocks), dim3(NT), 0, st, plans, ustart,
+                           nitems, total);
+        break;
+    case CO_FILL:
+        hipLaunchKernelGGL((batched_kernel<CO_FILL, 4>), dim3(blocks), dim3(NT), 0, st, plans, ustart,
+                           nitems, total);
+        break;
+    case CO_MUL_ACC:
+        hipLaunchKernelGGL((batched_kernel<CO_MUL_ACC, 4>), dim3(blocks), dim3(NT), 0, st, plans,
+                           ustart, nitems, total);
+        break;
+    case CO_MUL:
+        hipLaunchKernelGGL((batched_kernel<CO_MUL, 4>), dim3(blocks), dim3(NT), 0, st, plans, ustart,
+                           nitems, total);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace triot

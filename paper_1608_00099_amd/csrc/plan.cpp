@@ -1,0 +1,697 @@
+// Host planner: one validation pass over shapes per call (Section 4 of the
+// paper: "a single check over shapes rather than over indices"), then the
+// launch plan -- dropped and merged axes, vector width, the box split and
+// the magic-division tables of the kernels.
+#include "plan.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+namespace triot {
+
+bool magic_for(uint32_t c, AxisDiv *out)
+{
+    if (c < 2)
+        return false;
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < c)
+        ++l;                                   // l = ceil(log2 c), 1..32
+    uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - c)) / c + 1;
+    out->c = c;
+    out->m = (uint32_t)m;
+    out->s = l - 1;
+    out->pad = 0;
+    return true;
+}
+
+static AxisDiv trivial_div()
+{
+    AxisDiv a;
+    a.c = 1;
+    a.m = 0;
+    a.s = 0;
+    a.pad = 0;
+    return a;
+}
+
+int device_cus()
+{
+    static std::mutex mu;
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    std::lock_guard<std::mutex> g(mu);
+    if (!cached[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+bool is_segment_op(triot_op op)
+{
+    return op == TRIOT_OP_MOMENTS || op == TRIOT_OP_MOMENTS_ADJ;
+}
+
+// Checked arithmetic on non-negative int64 values.
+static bool mul_ok(int64_t a, int64_t b, int64_t *r)
+{
+    if (a == 0 || b == 0) {
+        *r = 0;
+        return true;
+    }
+    if (a > INT64_MAX / b)
+        return false;
+    *r = a * b;
+    return true;
+}
+
+static bool add_ok(int64_t a, int64_t b, int64_t *r)
+{
+    if (a > INT64_MAX - b)
+        return false;
+    *r = a + b;
+    return true;
+}
+
+// Which operands are read or written only where the tuple lies inside a
+// window (the rest must contain the whole counter), and which window.
+// role[k] = -1: must contain the counter; role[k] = j: predicated by
+// operand j's window extents.
+static void roles(triot_op op, int n, int role[MAXT])
+{
+    for (int k = 0; k < MAXT; ++k)
+        role[k] = -1;
+    if (op == TRIOT_OP_EMBED_FILL) {
+        role[1] = 1;
+    } else if (op == TRIOT_OP_MUL_ADJ) {
+        role[0] = 0;   // ga: its own window
+        role[1] = 1;   // gb: its own window
+        role[2] = 2;   // gout, a, b: the intersection (gout's window)
+        role[3] = 2;
+        role[4] = 2;
+    }
+    (void)n;
+}
+
+static bool is_output(triot_op op, int k)
+{
+    switch (op) {
+    case TRIOT_OP_COPY:
+    case TRIOT_OP_EMBED_FILL:
+    case TRIOT_OP_MUL_ACC:
+    case TRIOT_OP_MUL:
+    case TRIOT_OP_MOMENTS_ADJ:
+        return k == 0;
+    case TRIOT_OP_MUL_ADJ:
+        return k == 0 || k == 1;
+    default:
+        return false;
+    }
+}
+
+triot_status validate(triot_op op, int n, int d, const int64_t *shapes, const int64_t *counter,
+                      void *const *tensors, const int64_t *bases, const void *params, Request *r)
+{
+    std::memset(r, 0, sizeof(*r));
+    if ((int)op < 0 || (int)op > (int)TRIOT_OP_INDEX)
+        return TRIOT_E_INVALID;
+    bool n_ok = false;
+    switch (op) {
+    case TRIOT_OP_COPY:
+    case TRIOT_OP_EMBED_FILL: n_ok = (n == 2); break;
+    case TRIOT_OP_MUL_ACC:
+    case TRIOT_OP_MUL: n_ok = (n == 3); break;
+    case TRIOT_OP_MOMENTS: n_ok = (n >= 1 && n <= 4); break;
+    case TRIOT_OP_MOMENTS_ADJ: n_ok = (n == 1); break;
+    case TRIOT_OP_MUL_ADJ: n_ok = (n == 5); break;
+    case TRIOT_OP_INDEX: n_ok = (n >= 1 && n <= MAXT); break;
+    }
+    if (!n_ok)
+        return TRIOT_E_INVALID;
+    if (d < 0 || d > MAXD)
+        return TRIOT_E_DIM;
+    if ((d > 0 && !shapes) || !tensors)
+        return TRIOT_E_INVALID;
+    r->op = op;
+    r->n = n;
+    r->d = d;
+    r->params = params;
+    r->elem_bytes = 4;
+    if (op == TRIOT_OP_COPY || op == TRIOT_OP_EMBED_FILL) {
+        if (params) {
+            int eb = ((const triot_copy_params *)params)->elem_bytes;
+            if (eb != 4 && eb != 8)
+                return TRIOT_E_INVALID;
+            r->elem_bytes = eb;
+        }
+    } else if (op == TRIOT_OP_INDEX) {
+        r->elem_bytes = 8;  // int64 output; operands carry no data
+    } else if (op == TRIOT_OP_MOMENTS) {
+        if (params) {
+            int f = ((const triot_moments_params *)params)->flags;
+            if (f & ~(TRIOT_MOMENTS_FIRST | TRIOT_MOMENTS_COV))
+                return TRIOT_E_INVALID;
+        }
+    } else if (op == TRIOT_OP_MOMENTS_ADJ) {
+        if (!params)
+            return TRIOT_E_INVALID;
+        int f = ((const triot_moments_adj_params *)params)->flags;
+        if (f & ~(TRIOT_MOMENTS_FIRST | TRIOT_MOMENTS_COV))
+            return TRIOT_E_INVALID;
+    }
+
+    int64_t total[MAXT];
+    for (int k = 0; k < n; ++k) {
+        int64_t t = 1;
+        for (int i = 0; i < d; ++i) {
+            int64_t s = shapes[(size_t)k * d + i];
+            if (s < 0)
+                return TRIOT_E_INVALID;
+            r->shape[k][i] = s;
+            if (!mul_ok(t, s, &t))
+                return TRIOT_E_OVERFLOW;
+        }
+        int64_t bytes;
+        if (!mul_ok(t, (int64_t)r->elem_bytes, &bytes) || bytes > (INT64_MAX >> 2))
+            return TRIOT_E_OVERFLOW;
+        total[k] = t;
+        int64_t b = bases ? bases[k] : 0;
+        if (b < 0 || (t > 0 && b >= t) || (t == 0 && b != 0))
+            return TRIOT_E_BOUNDS;
+        r->base[k] = b;
+        r->ptr[k] = tensors[k];
+    }
+
+    // Window start tuple and available extents of every operand.
+    int64_t avail[MAXT][MAXD];
+    for (int k = 0; k < n; ++k) {
+        int64_t f = r->base[k];
+        for (int i = d - 1; i >= 0; --i) {
+            int64_t s = r->shape[k][i];
+            int64_t digit = s ? f % s : 0;
+            f = s ? f / s : 0;
+            avail[k][i] = s - digit;
+        }
+    }
+
+    // Counter: explicit, or the op's default.
+    for (int i = 0; i < d; ++i) {
+        int64_t c;
+        if (counter) {
+            c = counter[i];
+            if (c < 0)
+                return TRIOT_E_INVALID;
+        } else if (op == TRIOT_OP_EMBED_FILL || op == TRIOT_OP_MOMENTS_ADJ) {
+            c = avail[0][i];
+        } else if (op == TRIOT_OP_MUL_ADJ) {
+            c = std::max(avail[0][i], avail[1][i]);
+        } else {
+            c = avail[0][i];
+            for (int k = 1; k < n; ++k)
+                c = std::min(c, avail[k][i]);
+        }
+        r->counter[i] = c;
+    }
+    int64_t np = 1;
+    for (int i = 0; i < d; ++i)
+        if (!mul_ok(np, r->counter[i], &np))
+            return TRIOT_E_OVERFLOW;
+    r->npoints = np;
+
+    int role[MAXT];
+    roles(op, n, role);
+    for (int k = 0; k < n; ++k) {
+        if (role[k] >= 0)
+            continue;
+        for (int i = 0; i < d; ++i)
+            if (r->counter[i] > avail[k][i])
+                return TRIOT_E_BOUNDS;
+    }
+    if (op == TRIOT_OP_MUL_ADJ) {
+        // The intersection (gout's window) must lie inside a's and b's.
+        for (int i = 0; i < d; ++i)
+            if (avail[2][i] > avail[3][i] || avail[2][i] > avail[4][i])
+                return TRIOT_E_BOUNDS;
+    }
+    if (np == 0)
+        return TRIOT_OK;
+
+    for (int k = 0; k < n; ++k) {
+        if (op == TRIOT_OP_INDEX && k > 0)
+            continue;
+        if (!tensors[k])
+            return TRIOT_E_INVALID;
+    }
+    if (op == TRIOT_OP_INDEX) {
+        int64_t outb;
+        if (!mul_ok(np, (int64_t)n * 8, &outb))
+            return TRIOT_E_OVERFLOW;
+    }
+    if (op == TRIOT_OP_MOMENTS_ADJ) {
+        const triot_moments_adj_params *p = (const triot_moments_adj_params *)params;
+        if (!p->mom || !p->gmom)
+            return TRIOT_E_INVALID;
+    }
+
+    // Aliasing: byte range touched by each operand over the counter.
+    if (op != TRIOT_OP_INDEX && op != TRIOT_OP_MOMENTS) {
+        uint64_t lo[MAXT], hi[MAXT];
+        int64_t eb = (op == TRIOT_OP_COPY || op == TRIOT_OP_EMBED_FILL) ? r->elem_bytes : 4;
+        for (int k = 0; k < n; ++k) {
+            int64_t span = 0;
+            bool empty = false;
+            for (int i = 0; i < d; ++i) {
+                int64_t ext = r->counter[i];
+                if (role[k] >= 0)
+                    ext = std::min(ext, avail[role[k]][i]);
+                if (ext <= 0) {
+                    empty = true;
+                    break;
+                }
+                int64_t stride = 1;
+                for (int j = i + 1; j < d; ++j)
+                    stride *= r->shape[k][j];
+                span += (ext - 1) * stride;
+            }
+            uint64_t p = (uint64_t)(uintptr_t)tensors[k];
+            lo[k] = p + (uint64_t)r->base[k] * eb;
+            hi[k] = empty ? lo[k] : lo[k] + (uint64_t)(span + 1) * eb;
+        }
+        for (int o = 0; o < n; ++o) {
+            if (!is_output(op, o))
+                continue;
+            for (int k = 0; k < n; ++k) {
+                if (k == o || lo[o] == hi[o] || lo[k] == hi[k])
+                    continue;
+                bool overlap = lo[o] < hi[k] && lo[k] < hi[o];
+                if (!overlap)
+                    continue;
+                bool same_view = tensors[o] == tensors[k] && r->base[o] == r->base[k] &&
+                                 std::memcmp(r->shape[o], r->shape[k], sizeof(int64_t) * d) == 0;
+                if (!same_view || is_output(op, k))
+                    return TRIOT_E_ALIAS;
+            }
+        }
+    }
+    (void)total;
+    return TRIOT_OK;
+}
+
+// ---------------------------------------------------------------------
+// Element-wise plan
+// ---------------------------------------------------------------------
+
+struct Ax {
+    int64_t c;
+    int64_t S[MAXT];  // element (word) strides
+    int64_t B[MAXT];  // predicate extent, -1 when it can never fail
+};
+
+triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    CoPlan &P = out->plan;
+    const int n = r.n, d = r.d;
+    int role[MAXT];
+    roles(r.op, n, role);
+
+    // Window extents again (predicate bounds).
+    int64_t avail[MAXT][MAXD];
+    for (int k = 0; k < n; ++k) {
+        int64_t f = r.base[k];
+        for (int i = d - 1; i >= 0; --i) {
+            int64_t sz = r.shape[k][i];
+            int64_t digit = sz ? f % sz : 0;
+            f = sz ? f / sz : 0;
+            avail[k][i] = sz - digit;
+        }
+    }
+
+    // 1. Logical axes with their strides; drop extent-1 axes.
+    Ax ax[MAXD + 1];
+    int na = 0;
+    for (int i = 0; i < d; ++i) {
+        if (r.counter[i] == 1)
+            continue;
+        Ax a;
+        a.c = r.counter[i];
+        for (int k = 0; k < n; ++k) {
+            int64_t st = 1;
+            for (int j = i + 1; j < d; ++j)
+                st *= r.shape[k][j];
+            a.S[k] = st;
+            int64_t b = -1;
+            if (role[k] >= 0 && avail[role[k]][i] < a.c)
+                b = avail[role[k]][i];
+            a.B[k] = b;
+        }
+        ax[na++] = a;
+    }
+    int64_t base[MAXT];
+    for (int k = 0; k < n; ++k)
+        base[k] = r.base[k];
+
+    // 2. 8-byte elements move as two 4-byte words: a trailing word axis.
+    const bool words2 = (r.op == TRIOT_OP_COPY || r.op == TRIOT_OP_EMBED_FILL) && r.elem_bytes == 8;
+    if (words2) {
+        for (int i = 0; i < na; ++i)
+            for (int k = 0; k < n; ++k)
+                ax[i].S[k] *= 2;
+        for (int k = 0; k < n; ++k)
+            base[k] *= 2;
+        Ax w;
+        w.c = 2;
+        for (int k = 0; k < n; ++k) {
+            w.S[k] = 1;
+            w.B[k] = -1;
+        }
+        ax[na++] = w;
+    }
+    if (na == 0) {  // a scalar: one point
+        Ax a;
+        a.c = 1;
+        for (int k = 0; k < n; ++k) {
+            a.S[k] = 1;
+            a.B[k] = -1;
+        }
+        ax[na++] = a;
+    }
+
+    // 3. Merge adjacent axes where every operand is contiguous across them
+    //    and the inner one carries no live predicate (INDEX and the
+    //    element-wise ops only read addresses, never the tuple).
+    Ax m[MAXD + 1];
+    int nm = 0;
+    m[MAXD] = ax[na - 1];
+    int front = MAXD;
+    for (int i = na - 2; i >= 0; --i) {
+        Ax &b = m[front];
+        const Ax &a = ax[i];
+        bool ok = true;
+        for (int k = 0; k < n && ok; ++k) {
+            int64_t want;
+            if (b.B[k] != -1 || !mul_ok(b.c, b.S[k], &want) || a.S[k] != want)
+                ok = false;
+        }
+        int64_t merged_c;
+        if (ok && mul_ok(a.c, b.c, &merged_c)) {
+            Ax c;
+            c.c = merged_c;
+            for (int k = 0; k < n; ++k) {
+                c.S[k] = b.S[k];
+                c.B[k] = a.B[k] == -1 ? -1 : a.B[k] * b.c;
+            }
+            m[front] = c;
+        } else {
+            m[--front] = a;
+        }
+    }
+    for (int i = front; i <= MAXD; ++i)
+        m[nm++] = m[i];
+    const int D = nm;
+
+    // 4. Vector width: every operand contiguous on the inner axis, the inner
+    //    extent, every outer stride, base, window bound and address a
+    //    multiple of the width.
+    const Ax &in = m[D - 1];
+    int vec = 1;
+    if (r.op != TRIOT_OP_INDEX) {
+        for (int v = std::min(4, std::max(1, s.vec_max)); v > 1; v >>= 1) {
+            bool ok = (in.c % v) == 0 && in.c / v >= 2;
+            for (int k = 0; k < n && ok; ++k) {
+                if (in.S[k] != 1 || base[k] % v != 0 ||
+                    ((uintptr_t)r.ptr[k] % (4 * (uintptr_t)v)) != 0)
+                    ok = false;
+                if (in.B[k] != -1 && in.B[k] % v != 0)
+                    ok = false;
+                for (int i = 0; i < D - 1 && ok; ++i)
+                    if (m[i].S[k] % v != 0)
+                        ok = false;
+            }
+            if (ok) {
+                vec = v;
+                break;
+            }
+        }
+    }
+    const int64_t L = in.c / vec;
+    const uint32_t esz = 4u * vec;
+    if (L >= (int64_t(1) << 32))
+        return TRIOT_E_UNSUPPORTED;
+    for (int i = 0; i < D - 1; ++i)
+        if (m[i].c >= (int64_t(1) << 32))
+            return TRIOT_E_UNSUPPORTED;
+
+    int64_t is[MAXT];
+    for (int k = 0; k < n; ++k)
+        is[k] = (in.S[k] == 1 && vec > 1) ? 1 : in.S[k];  // in vector units
+    bool unit = true;
+    for (int k = 0; k < n; ++k)
+        if (is[k] != 1)
+            unit = false;
+    if ((int64_t)is[0] >= (int64_t(1) << 31))
+        return TRIOT_E_UNSUPPORTED;
+    for (int k = 0; k < n; ++k)
+        if (is[k] * (int64_t)esz >= (int64_t(1) << 31))
+            return TRIOT_E_UNSUPPORTED;
+
+    // 5. Box: the fewest low axes whose rows reach the unit size, within the
+    //    LDS table, the exact range of the row magic and 31-bit offsets.
+    const int nouter = D - 1;
+    int nlow = 0;
+    int64_t RB = 1;
+    int rb_cap = std::max(1, std::min(s.rb_max, RB_MAX));
+    for (int i = nouter - 1; i >= 0; --i) {
+        if (RB * L >= s.pe_target)
+            break;
+        int64_t rb2 = RB * m[i].c;
+        if (rb2 > rb_cap)
+            break;
+        if ((unsigned __int128)rb2 * L * L > ((unsigned __int128)1 << 32))
+            break;
+        bool ok = true;
+        for (int k = 0; k < n && ok; ++k) {
+            int64_t span = (L - 1) * is[k];
+            for (int j = i; j < nouter; ++j)
+                span += (m[j].c - 1) * (m[j].S[k] / vec);
+            if ((span + 1) * (int64_t)esz >= (int64_t(1) << 31))
+                ok = false;
+        }
+        if (!ok)
+            break;
+        RB = rb2;
+        nlow++;
+    }
+    const int nhigh = nouter - nlow;
+    int64_t nboxes = 1;
+    for (int i = 0; i < nhigh; ++i)
+        nboxes *= m[i].c;
+    if (nboxes >= (int64_t(1) << 32))
+        return TRIOT_E_UNSUPPORTED;
+
+    int64_t BE = RB * L;
+    int64_t pe_cap = s.pe_target;
+    if (RB == 1) {
+        for (int k = 0; k < n; ++k)
+            pe_cap = std::min<int64_t>(pe_cap, ((int64_t(1) << 31) / ((int64_t)esz * is[k])) - 1);
+    }
+    pe_cap = std::max<int64_t>(pe_cap, 1);
+    int64_t parts = (BE + pe_cap - 1) / pe_cap;
+    int64_t PE = (BE + parts - 1) / parts;
+    int64_t nunits = nboxes * parts;
+    if (nunits >= (int64_t(1) << 32) || BE >= (int64_t(1) << 32))
+        return TRIOT_E_UNSUPPORTED;
+
+    // 6. The kernel argument.
+    P.D = (uint32_t)D;
+    P.n = (uint32_t)n;
+    P.nhigh = (uint32_t)nhigh;
+    P.nlow = (uint32_t)nlow;
+    P.L = (uint32_t)L;
+    P.Lm = (RB > 1) ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)L - 1) / (uint64_t)L) : 0;
+    P.RB = (uint32_t)RB;
+    P.BE = (uint32_t)BE;
+    P.parts = (uint32_t)parts;
+    P.PE = (uint32_t)PE;
+    if (parts > 1)
+        magic_for((uint32_t)parts, &P.partdiv);
+    else
+        P.partdiv = trivial_div();
+    P.nunits = (uint32_t)nunits;
+    P.esz = esz;
+    P.vec = (uint32_t)vec;
+    P.unit = unit ? 1u : 0u;
+    uint32_t predmask = 0;
+    for (int i = 0; i < nouter; ++i) {
+        magic_for((uint32_t)m[i].c, &P.ax[i]);
+        for (int k = 0; k < n; ++k) {
+            P.stride[k][i] = m[i].S[k] / vec;
+            if (m[i].B[k] >= 0) {
+                P.bound[k][i] = (uint32_t)m[i].B[k];
+                predmask |= 1u << k;
+            } else {
+                P.bound[k][i] = NOBOUND;
+            }
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        P.istride[k] = (uint32_t)is[k];
+        if (in.B[k] >= 0) {
+            P.ibound[k] = (uint32_t)(in.B[k] / vec);
+            predmask |= 1u << k;
+        } else {
+            P.ibound[k] = NOBOUND;
+        }
+        P.base[k] = base[k] / vec;
+        P.ptr[k] = (uint64_t)(uintptr_t)r.ptr[k];
+    }
+    // A predicated operand whose window is empty on some axis is never touched.
+    P.predmask = predmask;
+    P.npoints = (uint64_t)r.npoints;
+
+    int blocks = (int)std::min<int64_t>(nunits, (int64_t)cus * std::max(1, s.blocks_per_cu));
+    if (blocks > 8)
+        blocks = (blocks + 7) / 8 * 8;
+    out->blocks = std::max(blocks, 1);
+    out->unroll = s.unroll;
+    out->rows1 = (RB == 1);
+    out->unit = unit;
+    return TRIOT_OK;
+}
+
+// ---------------------------------------------------------------------
+// Row-segment plan (moments, moments adjoint)
+// ---------------------------------------------------------------------
+
+triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    SegPlan &P = out->plan;
+    const int n = r.n, d = r.d;
+    int flags = TRIOT_MOMENTS_FIRST;
+    if (r.op == TRIOT_OP_MOMENTS && r.params)
+        flags |= ((const triot_moments_params *)r.params)->flags;
+    if (r.op == TRIOT_OP_MOMENTS_ADJ)
+        flags |= ((const triot_moments_adj_params *)r.params)->flags;
+
+    int kept[MAXD];
+    int D = 0;
+    for (int i = 0; i < d; ++i)
+        if (r.counter[i] != 1)
+            kept[D++] = i;
+    const bool scalar = (D == 0);
+    if (scalar)
+        D = 1;
+    if (flags & TRIOT_MOMENTS_COV) {
+        if (D > 8)
+            return TRIOT_E_UNSUPPORTED;
+    }
+    int64_t c[MAXD];
+    for (int i = 0; i < D; ++i)
+        c[i] = scalar ? 1 : r.counter[kept[i]];
+    int64_t rows = 1;
+    for (int i = 0; i < D - 1; ++i)
+        rows *= c[i];
+    if (rows >= (int64_t(1) << 32))
+        return TRIOT_E_UNSUPPORTED;
+    for (int i = 0; i < D; ++i)
+        if (c[i] >= (int64_t(1) << 32))
+            return TRIOT_E_UNSUPPORTED;
+    const int64_t L = c[D - 1];
+    const int64_t S = std::min<int64_t>(L, SEG_MAX);
+    const int64_t G = (L + S - 1) / S;
+
+    P.D = (uint32_t)D;
+    P.n = (uint32_t)n;
+    P.d_orig = (uint32_t)d;
+    P.L = (uint32_t)L;
+    P.S = (uint32_t)S;
+    P.G = (uint32_t)G;
+    if (G > 1)
+        magic_for((uint32_t)G, &P.gdiv);
+    else
+        P.gdiv = trivial_div();
+    P.rows = (uint32_t)rows;
+    P.flags = (uint32_t)flags;
+    P.nseg = (uint64_t)rows * (uint64_t)G;
+    P.ntiles = (P.nseg + NT - 1) / NT;
+    for (int i = 0; i < D - 1; ++i)
+        magic_for((uint32_t)c[i], &P.ax[i]);
+    for (int i = 0; i < D; ++i) {
+        P.center[i] = 0.5 * (double)(c[i] - 1);
+        P.orig[i] = scalar ? 0xFFFFFFFFu : (uint32_t)kept[i];
+    }
+    bool full = true;
+    for (int k = 0; k < n; ++k) {
+        int64_t want = 1;
+        for (int i = D - 1; i >= 0; --i) {
+            int64_t st = 1;
+            if (!scalar)
+                for (int j = kept[i] + 1; j < d; ++j)
+                    st *= r.shape[k][j];
+            P.stride[k][i] = st;
+            if (st != want)
+                full = false;
+            want *= c[i];
+        }
+        P.base[k] = r.base[k];
+        P.ptr[k] = (uint64_t)(uintptr_t)r.ptr[k];
+    }
+    P.full = full ? 1u : 0u;
+    const bool cov = (flags & TRIOT_MOMENTS_COV) != 0;
+    // Accumulator slots of the kernel tier: M, DMAX first sums and, with
+    // the covariance, DMAX(DMAX+1)/2 second sums (DMAX = 8 or 32).
+    const int dmax = (D <= 8) ? 8 : 32;
+    P.nterms = (uint32_t)(1 + dmax + (cov ? dmax * (dmax + 1) / 2 : 0));
+
+    int64_t blocks = std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * 4);
+    if (blocks > 8)
+        blocks = (blocks + 7) / 8 * 8;
+    blocks = std::max<int64_t>(blocks, 1);
+    P.nblocks = (uint32_t)blocks;
+    out->blocks = (int)blocks;
+    out->dmax = dmax;
+    return TRIOT_OK;
+}
+
+size_t segment_workspace_bytes(const SegLaunch &l)
+{
+    // Per-block partial sums (float64) after a 256-byte header holding the
+    // completion ticket.
+    return 256 + (size_t)l.plan.nblocks * l.plan.nterms * sizeof(double);
+}
+
+std::string sched_key(const Request &r)
+{
+    std::string k;
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "op%d:n%d:e%d:d%d", (int)r.op, r.n, r.elem_bytes, r.d);
+    k += buf;
+    k += ":c";
+    for (int i = 0; i < r.d; ++i) {
+        std::snprintf(buf, sizeof buf, "%lld,", (long long)r.counter[i]);
+        k += buf;
+    }
+    for (int t = 0; t < r.n; ++t) {
+        k += ":s";
+        for (int i = 0; i < r.d; ++i) {
+            std::snprintf(buf, sizeof buf, "%lld,", (long long)r.shape[t][i]);
+            k += buf;
+        }
+        std::snprintf(buf, sizeof buf, "b%lld,a%d", (long long)(r.base[t] % 4),
+                      (int)((uintptr_t)r.ptr[t] % 16));
+        k += buf;
+    }
+    return k;
+}
+
+}  // namespace triot

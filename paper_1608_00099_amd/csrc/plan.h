@@ -1,0 +1,67 @@
+// Host planner: validation (once per call over shapes, Section 4) and the
+// launch plan of one co-iteration.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "common.h"
+
+namespace triot {
+
+// Launch schedule knobs (defaults, or the autotuner's choice).
+struct Sched {
+    int vec_max = 4;        // widest vector (words) allowed: 1, 2 or 4
+    int unroll = 4;         // elements per thread per step: 2, 4 or 8
+    int blocks_per_cu = 4;  // persistent workgroups per CU
+    int rb_max = RB_MAX;    // rows per box (LDS table) upper bound
+    int pe_target = 8192;   // elements per work unit
+};
+
+// One validated, normalized request.
+struct Request {
+    triot_op op;
+    int n;                           // operands
+    int d;
+    int64_t shape[MAXT][MAXD];
+    int64_t counter[MAXD];
+    int64_t base[MAXT];
+    void *ptr[MAXT];
+    int elem_bytes;                  // element size of COPY / EMBED_FILL (4 or 8), else 4
+    int64_t npoints;                 // counter points
+    const void *params;
+};
+
+struct CoLaunch {
+    CoPlan plan;
+    int blocks;
+    int unroll;
+    bool rows1;     // RB == 1
+    bool unit;      // every inner stride is 1
+};
+
+struct SegLaunch {
+    SegPlan plan;
+    int blocks;
+    int dmax;       // register tier of the accumulators (8 or 32)
+};
+
+// Number of compute units of the current device (cached per device).
+int device_cus();
+
+triot_status validate(triot_op op, int n, int d, const int64_t *shapes, const int64_t *counter,
+                      void *const *tensors, const int64_t *bases, const void *params, Request *r);
+
+bool is_segment_op(triot_op op);
+
+triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *out);
+triot_status plan_segment(const Request &r, int cus, SegLaunch *out);
+
+size_t segment_workspace_bytes(const SegLaunch &l);
+
+// Key of the schedule cache: everything the plan shape depends on.
+std::string sched_key(const Request &r);
+
+}  // namespace triot

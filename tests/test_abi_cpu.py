@@ -1,0 +1,171 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every symbol include/triot.h declares, validation returns the
+documented codes, the magic-division constants are exact, and the planner
+drops and merges axes as described."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1608_00099_amd import _lib as L
+from paper_1608_00099_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "triot.h")
+
+# Fake, non-overlapping device addresses: planning never dereferences them.
+P0, P1, P2, P3, P4 = [(k + 1) << 40 for k in range(5)]
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(triot_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_and_library_exports_every_entry_point():
+    names = declared_functions()
+    assert "triot_apply" in names and "triot_apply_batched" in names
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), "libtriot.so does not export %s" % n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_status_strings():
+    for s in range(9):
+        assert L.status_string(s)
+    assert L.status_string(0) == "ok"
+
+
+def _apply(op, shapes, counter=None, ptrs=None, bases=None, params=None, out=0, ws=0, wsb=0):
+    d = len(shapes[0]) if shapes else 0
+    ptrs = ptrs if ptrs is not None else [P0, P1, P2, P3, P4][: len(shapes)]
+    return L.triot_apply(op, len(shapes), d, shapes, counter, ptrs, bases, params, out, ws, wsb, 0)
+
+
+def test_validation_codes():
+    # wrong operand count / op
+    assert _apply(L.OP_COPY, [(4,), (4,), (4,)]) == L.E_INVALID
+    assert L.triot_apply(99, 2, 1, [(4,), (4,)], None, [P0, P1], None, None, 0, 0, 0, 0) == L.E_INVALID
+    # dimension
+    assert L.triot_apply(L.OP_COPY, 2, 33, [(1,) * 33, (1,) * 33], None, [P0, P1], None, None,
+                         0, 0, 0, 0) == L.E_DIM
+    assert L.triot_apply(L.OP_COPY, 2, -1, [], None, [P0, P1], None, None, 0, 0, 0, 0) == L.E_DIM
+    # counter beyond an operand (the paper's bounds check)
+    assert _apply(L.OP_COPY, [(4, 4), (3, 5)], counter=(4, 4)) == L.E_BOUNDS
+    # window beyond the parent
+    assert _apply(L.OP_COPY, [(6, 6), (6, 6)], counter=(3, 3), bases=[4 * 6, 0]) == L.E_BOUNDS
+    assert _apply(L.OP_COPY, [(6, 6), (6, 6)], counter=(3, 3), bases=[36, 0]) == L.E_BOUNDS
+    # null pointer with work
+    assert _apply(L.OP_COPY, [(4,), (4,)], ptrs=[P0, 0]) == L.E_INVALID
+    # null pointers without work are fine: extent 0 is a no-op
+    assert _apply(L.OP_COPY, [(4, 0), (4, 0)], ptrs=[0, 0]) == L.OK
+    # partial overlap of the output with an input
+    assert _apply(L.OP_COPY, [(8,), (8,)], counter=(8,), ptrs=[P0, P0 + 8]) == L.E_ALIAS
+    assert _apply(L.OP_MUL_ACC, [(8,), (8,), (8,)], ptrs=[P0, P0 + 4, P2]) == L.E_ALIAS
+    # the exact same view as input of an element-wise op is allowed
+    st, _ = L.triot_plan_describe(L.OP_MUL_ACC, 3, 1, [(8,), (8,), (8,)], None, [P0, P1, P0])
+    assert st == L.OK
+    # overflow of an int64 size
+    big = (1 << 31, 1 << 31, 1 << 3)
+    assert _apply(L.OP_COPY, [big, big], counter=(1, 1, 1)) == L.E_OVERFLOW
+    # bad params
+    assert _apply(L.OP_COPY, [(4,), (4,)], params=L.CopyParams(3)) == L.E_INVALID
+    assert _apply(L.OP_MOMENTS_ADJ, [(4,)]) == L.E_INVALID
+    # moments need a workspace and an output
+    assert _apply(L.OP_MOMENTS, [(4, 4)], out=P3) == L.E_WORKSPACE
+    assert _apply(L.OP_MOMENTS, [(4, 4)], out=0, ws=P2, wsb=1 << 20) == L.E_INVALID
+    # covariance beyond 8 axes is outside this build's limits
+    shp = (2,) * 9
+    st = _apply(L.OP_MOMENTS, [shp], out=P3, ws=P2, wsb=1 << 30,
+                params=L.MomentsParams(L.MOMENTS_FIRST | L.MOMENTS_COV, None))
+    assert st == L.E_UNSUPPORTED
+
+
+def _magic_div(n, m, s):
+    h = (n * m) >> 32
+    return (h + ((n - h) >> 1)) >> s
+
+
+def test_magic_division_exact_for_all_small_divisors():
+    """Every divisor 2..2^16 against boundary numerators and random samples
+    (Granlund & Montgomery's round-up method must equal floor division)."""
+    rng = np.random.default_rng(0)
+    top = (1 << 32) - 1
+    cs = np.arange(2, (1 << 16) + 1, dtype=np.uint64)
+    ms = np.empty_like(cs)
+    ss = np.empty_like(cs)
+    for i, c in enumerate(cs):
+        st, m, s = L.triot_divmod_magic(int(c))
+        assert st == L.OK
+        ms[i], ss[i] = m, s
+    for k in [0, 1, 2, 3]:
+        # numerators: 0, c-1, c, k*c - 1 near the top, 2^32 - 1, random
+        nums = [np.zeros_like(cs), cs - 1, cs, (top // cs) * cs - 1, (top // cs) * cs,
+                np.full_like(cs, top), rng.integers(0, top, size=cs.size, dtype=np.uint64)][k::4]
+        for n in nums:
+            h = (n * ms) >> np.uint64(32)
+            q = (h + ((n - h) >> np.uint64(1))) >> ss
+            assert np.array_equal(q, n // cs)
+
+
+def test_magic_division_large_divisors():
+    rng = np.random.default_rng(1)
+    top = (1 << 32) - 1
+    for c in list(rng.integers(1 << 16, top, size=2000)) + [top, top - 1, (1 << 31) + 1, 1 << 31]:
+        c = int(c)
+        st, m, s = L.triot_divmod_magic(c)
+        assert st == L.OK
+        for n in [0, c - 1, c, min(2 * c - 1, top), top, int(rng.integers(0, top))]:
+            assert _magic_div(n, m, s) == n // c
+    assert L.triot_divmod_magic(1)[0] == L.E_INVALID
+    assert L.triot_divmod_magic(0)[0] == L.E_INVALID
+
+
+def test_plan_drops_extent_one_and_merges_full_axes():
+    # cfg1: (48,40,36) into (64,64,64): nothing merges, inner extent 36
+    p = api.describe(L.OP_COPY, [(64, 64, 64), (48, 40, 36)], counter=(48, 40, 36))
+    assert p["dims"] == 3 and p["extents"] == [48, 40, 36]
+    assert p["vec"] == 4                      # 36 and the strides are multiples of 4
+    # a full operand pair collapses to one flat axis
+    p = api.describe(L.OP_MUL_ACC, [(16,) * 6] * 3)
+    assert p["dims"] == 1 and p["extents"] == [16 ** 6]
+    # extent-1 counter axes are dropped
+    p = api.describe(L.OP_COPY, [(5, 7, 9), (5, 7, 9)], counter=(5, 1, 9))
+    assert p["dims"] == 2 and p["extents"] == [5, 9]
+    # the differentiable workload's product: (28,30,32,26,32) in 32^5
+    p = api.describe(L.OP_MUL, [(28, 30, 32, 26, 32), (32,) * 5, (28, 30, 32, 26, 32)])
+    assert p["extents"] == [28, 960, 832]
+    # 8-byte copies move two words per element
+    p = api.describe(L.OP_COPY, [(10, 10), (6, 7)], counter=(6, 7), params=L.CopyParams(8))
+    assert p["extents"] == [6, 14]
+    # scalars
+    p = api.describe(L.OP_COPY, [(), ()])
+    assert p["dims"] == 1 and p["extents"] == [1]
+
+
+def test_plan_box_split_limits():
+    # very short rows: the box tabulates several low axes (bounded table)
+    p = api.describe(L.OP_COPY, [(9, 5, 13, 21, 14, 6, 3, 25)] * 1 + [(10, 6, 14, 22, 15, 7, 4, 26)],
+                     counter=(9, 5, 13, 21, 14, 6, 3, 25))
+    assert p["box_rows"] <= 256
+    assert p["low_axes"] >= 1
+    assert p["units"] >= p["blocks"]
+    # one very long row: a single-row box split into units
+    p = api.describe(L.OP_COPY, [(1 << 24,), (1 << 24,)])
+    assert p["box_rows"] == 1 and p["units"] > 1
+
+
+def test_segment_plan_for_moments():
+    p = api.describe(L.OP_MOMENTS, [(16,) * 6])
+    assert p["kernel"] == 1 and p["dims"] == 6 and p["extents"] == [16] * 6
+    p = api.describe(L.OP_MOMENTS, [(3, 1, 5)])
+    assert p["dims"] == 2 and p["extents"] == [3, 5]
+
+
+def test_workspace_size():
+    assert L.triot_workspace_size(L.OP_COPY, 2, 1, [(4,), (4,)]) == 0
+    n = L.triot_workspace_size(L.OP_MOMENTS, 1, 6, [(16,) * 6])
+    assert n > 256
