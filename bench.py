@@ -1,0 +1,453 @@
+#!/usr/bin/env python3
+"""Benchmark of the co-iteration hot path on one MI355X.
+
+One step = the run-time-dimension sweep d = 2..8 (the workload the headline
+metric is quoted on): for every d, a zero-pad embedding of a ~2^26-element
+float32 tensor into a shape enlarged by 1..16 per axis (COPY over the source
+shape into a pre-zeroed destination) and x[t] += y[t]*z[t] over the
+intersection of three shapes (MUL_ACC).  All tensors are resident in HBM
+before timing.  `value` is the effective HBM bandwidth of the whole step:
+algorithmic bytes (8 B per copied point, 16 B per x += y*z point) divided by
+the step time.
+
+Also reported on the same line: the roofline of the dominant kernel (HIP
+events around its launches), the CPU oracle on a bounded sample of the same
+workload, and per-configuration figures for the other parts of the hot path
+(moments, batched padding for FFT convolution, the differentiable pipeline,
+the small pad-embed) next to a plain device-copy ceiling.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def prod(s):
+    p = 1
+    for v in s:
+        p *= int(v)
+    return p
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("common.h", "kern_coiter.hip", "kern_segment.hip", "plan.cpp"):
+        with open(os.path.join(ROOT, "paper_1608_00099_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# ---------------------------------------------------------------------------
+# GPU workload
+# ---------------------------------------------------------------------------
+
+class Sweep:
+    """The d = 2..8 sweep, resident on the device."""
+
+    def __init__(self, dev, log2_target=26):
+        import torch
+        from paper_1608_00099_amd import inputs
+        self.items = []
+        seed = 1000
+        for d in range(2, 9):
+            src_s, dst_s = inputs.cfg2_pad_shapes(d, log2_target)
+            xs, ys, zs = inputs.cfg2_inter_shapes(d, log2_target)
+            src = inputs.uniform_torch(src_s, seed + 10 * d + 0, dev)
+            dst = torch.zeros(dst_s, dtype=torch.float32, device=dev)
+            x = inputs.uniform_torch(xs, seed + 10 * d + 1, dev)
+            y = inputs.uniform_torch(ys, seed + 10 * d + 2, dev)
+            z = inputs.uniform_torch(zs, seed + 10 * d + 3, dev)
+            self.items.append(dict(d=d, src=src, dst=dst, x=x, y=y, z=z, src_s=src_s, dst_s=dst_s,
+                                   xs=xs, ys=ys, zs=zs))
+        torch.cuda.synchronize()
+
+    def launches(self):
+        """[(name, op, callable, algorithmic bytes)] of one step."""
+        from paper_1608_00099_amd import api
+        from paper_1608_00099_amd import _lib as L
+        out = []
+        for it in self.items:
+            out.append(("copy d=%d" % it["d"], L.OP_COPY,
+                        (lambda it=it: api.pad_embed_into(it["dst"], it["src"])),
+                        8 * prod(it["src_s"]), it))
+            out.append(("mul_acc d=%d" % it["d"], L.OP_MUL_ACC,
+                        (lambda it=it: api.mul_acc_(it["x"], it["y"], it["z"])),
+                        16 * prod(it["xs"]), it))
+        return out
+
+
+def plan_of(op, it):
+    from paper_1608_00099_amd import api
+    if op == 0:
+        shapes, counter = [it["dst_s"], it["src_s"]], it["src_s"]
+        ptrs = [it["dst"].data_ptr(), it["src"].data_ptr()]
+    else:
+        shapes, counter = [it["xs"], it["ys"], it["zs"]], None
+        ptrs = [it["x"].data_ptr(), it["y"].data_ptr(), it["z"].data_ptr()]
+    p = api.describe(op, shapes, counter=counter, ptrs=ptrs)
+    return p, api.kernel_name(op, p)
+
+
+def autotune_all(launches):
+    """Let the library's autotuner pick each launch's schedule (it times the
+    candidates with HIP events on these very buffers)."""
+    from paper_1608_00099_amd import api
+    from paper_1608_00099_amd import _lib as L
+    out = {}
+    for name, op, fn, nbytes, it in launches:
+        if op == L.OP_COPY:
+            api.autotune(op, [it["dst"], it["src"]], counter=it["src_s"], params=L.CopyParams(4))
+        else:
+            api.autotune(op, [it["x"], it["y"], it["z"]])
+        plan, kname = plan_of(op, it)
+        out[name] = {"unroll": plan["unroll"], "blocks": plan["blocks"], "vec": plan["vec"],
+                     "box_rows": plan["box_rows"]}
+    return out
+
+
+def time_steps(fns, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        for f in fns:
+            f()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        for f in fns:
+            f()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
+
+
+def per_launch(launches, reps=5):
+    """Median duration (ms) of every launch, from HIP events recorded on the
+    stream the kernels run on (the library uses torch's current stream).
+    Each timed launch follows an untimed one, so the device is still busy
+    while the host enqueues the event pair and the kernel between them."""
+    import torch
+    s = torch.cuda.current_stream()
+    res = {}
+    for name, op, fn, nbytes, it in launches:
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            fn()
+            a.record(s)
+            fn()
+            b.record(s)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        ms.sort()
+        res[name] = (ms[len(ms) // 2], ms[0], ms[-1])
+    return res
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on a bounded sample of the same workload
+# ---------------------------------------------------------------------------
+
+def cpu_baseline(log2_target):
+    import numpy as np
+    import oracle
+    from paper_1608_00099_amd import inputs
+    total_bytes, total_s = 0, 0.0
+    for d in range(2, 9):
+        src_s, dst_s = inputs.cfg2_pad_shapes(d, log2_target)
+        src = inputs.uniform(2, src_s, 90, d)
+        dst = np.zeros(prod(dst_s), dtype=np.float32)
+        t0 = time.perf_counter()
+        oracle.copy(src_s, dst, dst_s, src.reshape(-1), src_s)
+        total_s += time.perf_counter() - t0
+        total_bytes += 8 * prod(src_s)
+        del src, dst
+        xs, ys, zs = inputs.cfg2_inter_shapes(d, log2_target)
+        x = inputs.uniform(2, xs, 91, d).reshape(-1)
+        y = inputs.uniform(2, ys, 92, d).reshape(-1)
+        z = inputs.uniform(2, zs, 93, d).reshape(-1)
+        t0 = time.perf_counter()
+        oracle.mul_acc(xs, x, xs, y, ys, z, zs)
+        total_s += time.perf_counter() - t0
+        total_bytes += 16 * prod(xs)
+        del x, y, z
+        log("cpu oracle d=%d done (%.1f s so far)" % (d, total_s))
+    return total_bytes / total_s / 1e9, total_s
+
+
+# ---------------------------------------------------------------------------
+# Extras: the other configurations of the hot path
+# ---------------------------------------------------------------------------
+
+def event_ms(fn, reps=10, warm=2, pre=None, cover=True):
+    """Median/min/max ms of fn between HIP events.  `pre` (e.g. a cache
+    flush) runs before every timed call; otherwise an untimed call of fn
+    covers the host's enqueue latency (cover=False: fn alone, host-bound)."""
+    import torch
+    s = torch.cuda.current_stream()
+    for _ in range(warm):
+        if pre:
+            pre()
+        fn()
+    ms = []
+    for _ in range(reps):
+        if pre:
+            pre()
+        elif cover:
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    ms.sort()
+    return {"median_ms": ms[len(ms) // 2], "min_ms": ms[0], "max_ms": ms[-1]}
+
+
+def graph_ms(fn, reps=10):
+    """GPU time of fn's launches captured once in a torch CUDA graph and
+    replayed (no host work between the kernels)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    t = event_ms(g.replay, reps=reps, warm=1)
+    del g
+    return t
+
+
+def extras(dev):
+    import numpy as np
+    import torch
+    from paper_1608_00099_amd import api, autograd, inputs
+    from paper_1608_00099_amd import _lib as L
+    out = {}
+    # 1 GiB streaming-copy ceiling (torch's device copy)
+    n = 1 << 28
+    a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    t = event_ms(lambda: b.copy_(a))
+    out["copy_ceiling"] = {"GBs": 2 * 4 * n / t["median_ms"] / 1e6, "bytes": 8 * n,
+                           "what": "torch device copy of 1 GiB"}
+    flush = b  # scratch written between cold runs (>= 1 GiB beats the 256 MB cache)
+    del a
+    log("ceiling done")
+
+    # cfg1: small pad-embed (launch-latency bound)
+    src = torch.from_numpy(inputs.cfg1_values()).to(dev)
+    dst = torch.zeros(inputs.CFG1_DST, dtype=torch.float32, device=dev)
+    nb = 8 * prod(inputs.CFG1_SRC)
+    t = graph_ms(lambda: [api.pad_embed_into(dst, src) for _ in range(100)], reps=10)
+    per = t["median_ms"] / 100
+    out["cfg1_pad_embed"] = {"ms_per_launch": per, "GBs": nb / per / 1e6, "bytes": nb,
+                             "cache": "warm", "timing": "100 launches captured in one graph"}
+
+    # cfg3: moments of a 16^6 PMF (64 MiB: cold runs flush the cache first)
+    p = torch.from_numpy(inputs.cfg3_values()).to(dev)
+    nb = 4 * p.numel()
+    o32, o64 = api.moments(p, cov=True)
+    t_cold = event_ms(lambda: api.moments(p, cov=True), pre=lambda: flush.fill_(0.0))
+    t_warm = event_ms(lambda: api.moments(p, cov=True))
+    out["cfg3_moments_cov"] = {"cold": dict(t_cold, GBs=nb / t_cold["median_ms"] / 1e6),
+                               "warm": dict(t_warm, GBs=nb / t_warm["median_ms"] / 1e6),
+                               "bytes": nb}
+    log("moments done")
+
+    # cfg4: 4096 ragged pads for FFT convolution, one persistent graph launch
+    shapes = inputs.cfg4_shapes()
+    xs = [torch.from_numpy(x).to(dev) for x in inputs.cfg4_values(shapes)]
+    dsts = [torch.empty(inputs.padded_shape(sx, sy), dtype=torch.float32, device=dev)
+            for sx, sy in shapes]
+    nb = sum(4 * d_.numel() + 4 * x.numel() for d_, x in zip(dsts, xs))
+    items = [[d_, x] for d_, x in zip(dsts, xs)]
+    batch = api.Batch()
+    t0 = time.perf_counter()
+    batch.apply(L.OP_EMBED_FILL, items)          # plan, upload, capture, launch
+    torch.cuda.synchronize()
+    t_plan = (time.perf_counter() - t0) * 1e3
+    t_b = event_ms(batch.launch, reps=20)        # replay of the captured launch
+    info = batch.info()
+    t_pe = event_ms(lambda: [api.embed_fill_(d_, x) for d_, x in zip(dsts, xs)], reps=3, warm=1,
+                    cover=False)
+    t_pg = graph_ms(lambda: [api.embed_fill_(d_, x) for d_, x in zip(dsts, xs)], reps=5)
+    out["cfg4_batched_pad"] = {
+        "batched": dict(t_b, GBs=nb / t_b["median_ms"] / 1e6, first_call_ms=t_plan, **info),
+        "plain_per_item_eager": dict(t_pe, GBs=nb / t_pe["median_ms"] / 1e6, launches=len(items)),
+        "plain_per_item_graph": dict(t_pg, GBs=nb / t_pg["median_ms"] / 1e6, launches=len(items)),
+        "speedup_vs_plain_eager": t_pe["median_ms"] / t_b["median_ms"],
+        "speedup_vs_plain_graph": t_pg["median_ms"] / t_b["median_ms"],
+        "bytes": nb, "items": len(items)}
+    batch.close()
+    del xs, dsts, items
+    log("batched done")
+
+    # cfg5: differentiable pipeline, autograd vs the raw kernels
+    x_np, w_np, lam_np = inputs.cfg5_values()
+    x = torch.from_numpy(x_np).to(dev).requires_grad_(True)
+    w = torch.from_numpy(w_np).to(dev).requires_grad_(True)
+    lam = torch.from_numpy(lam_np.astype(np.float32)).to(dev)
+
+    def fwd_bwd():
+        P = autograd.pad_embed(x, inputs.CFG5_P)
+        y = autograd.mul(P, w)
+        M, E, C = autograd.moments(y)
+        loss = (lam * E).sum()
+        loss.backward()
+        return loss
+
+    t_auto = event_ms(fwd_bwd, reps=10)
+    xd, wd = x.detach(), w.detach()
+
+    def raw():
+        P = api.pad_embed(xd, inputs.CFG5_P)
+        y = api.mul(P, wd)
+        o32, o64 = api.moments(y, cov=False)
+        gm = torch.zeros(1 + 5, dtype=torch.float32, device=dev)
+        gy = api.moments_adj(inputs.CFG5_W, o64, gm, cov=False)
+        gP, gw = api.mul_adj(gy, P, wd)
+        api.crop(gP, inputs.CFG5_X)
+
+    t_raw = event_ms(raw, reps=10)
+    fwd_bytes = (4 * prod(inputs.CFG5_P) + 4 * prod(inputs.CFG5_X) + 12 * prod(inputs.CFG5_W)
+                 + 4 * prod(inputs.CFG5_W))
+    bwd_bytes = (4 * prod(inputs.CFG5_W) + 20 * prod(inputs.CFG5_W)
+                 + 4 * (prod(inputs.CFG5_P) - prod(inputs.CFG5_W)) + 8 * prod(inputs.CFG5_X))
+    out["cfg5_autograd"] = {"autograd_fwd_bwd": t_auto, "raw_kernels": t_raw,
+                            "autograd_over_raw": t_auto["median_ms"] / t_raw["median_ms"],
+                            "GBs_raw": (fwd_bytes + bwd_bytes) / t_raw["median_ms"] / 1e6,
+                            "bytes": fwd_bytes + bwd_bytes}
+    log("autograd done")
+    return out
+
+
+def load_traffic(kernel, src_hash):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel)
+    if not e or e.get("source_hash") != src_hash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (default schedules)")
+    ap.add_argument("--cpu-log2", type=float, default=25.5,
+                    help="log2 elements per tensor of the CPU oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1608_00099_amd import _lib as L
+    L.lib()
+    dev = torch.device("cuda:0")
+    log("allocating the d=2..8 sweep")
+    sw = Sweep(dev)
+    launches = sw.launches()
+    tuned = {}
+    if not args.no_tune:
+        log("autotuning the %d launch schedules" % len(launches))
+        tuned = autotune_all(launches)
+    step_bytes = sum(x[3] for x in launches)
+    fns = [x[2] for x in launches]
+    log("timing %d steps after %d warm-up steps" % (args.steps, args.warmup))
+    ms_step, wall_ms = time_steps(fns, args.steps, args.warmup)
+    value = step_bytes / (ms_step * 1e-3) / 1e9
+    log("step %.3f ms, %.1f GB/s" % (ms_step, value))
+
+    # Per-launch durations and the dominant kernel's roofline.
+    pl = per_launch(launches)
+    per_op = {}
+    by_kernel = {}
+    for name, op, fn, nbytes, it in launches:
+        plan, kname = plan_of(op, it)
+        med = pl[name][0]
+        per_op[name] = {"ms": med, "GBs": nbytes / med / 1e6, "bytes": nbytes, "kernel": kname,
+                        "box_rows": plan["box_rows"], "units": plan["units"]}
+        k = by_kernel.setdefault(kname, {"ms": 0.0, "bytes": 0, "launches": 0})
+        k["ms"] += med
+        k["bytes"] += nbytes
+        k["launches"] += 1
+    dom = max(by_kernel, key=lambda k: by_kernel[k]["ms"])
+    dk = by_kernel[dom]
+    avg_ms = dk["ms"] / dk["launches"]
+    avg_bytes = dk["bytes"] / dk["launches"]
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = load_traffic(dom, src_hash)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic, "kernel": dom, "launches_per_step": dk["launches"],
+                "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": int(avg_bytes)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (sample 2^%g elements per tensor)" % args.cpu_log2)
+        gbs, secs = cpu_baseline(args.cpu_log2)
+        cpu = {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": "the same d=2..8 copy + x+=y*z recipe at 2^%g elements per tensor, "
+                         "single-threaded C oracle, %.1f s" % (args.cpu_log2, secs)}
+
+    ext = None
+    if not args.no_extras:
+        ext = extras(dev)
+
+    line = {
+        "metric": "effective HBM GB/s & % of peak; batched/autograd vs plain kernels, same GPU",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "runtime-dimension sweep d=2..8, ~2^26 float32 elements per tensor: "
+                               "pad-embed (+1..16 per axis) and x+=y*z over the intersection of "
+                               "three shapes",
+                   "bytes_per_step": step_bytes, "pct_of_peak": round(100 * value / PEAK_HBM_GBS, 2),
+                   "wall_ms_per_step": round(wall_ms, 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_op": per_op,
+        "tuned": tuned,
+        "extras": ext,
+        "kernel_source": src_hash,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -92,8 +92,9 @@ typedef enum triot_op {
      * TRIOT_MOMENTS_COV, by the upper triangle C_00, C_01, .., C_0(d-1),
      * C_11, .., C_(d-1)(d-1): 1 + d (+ d(d+1)/2) values.
      * params: const triot_moments_params*.  Accumulation is float64 per
-     * thread and compensated (TwoSum) across blocks; the result is
+     * thread and compensated (TwoSum) across workgroups; the result is
      * deterministic for a given device and launch.  Needs a workspace.
+     * Enqueues two kernels (partial sums, then their combination).
      * Limits: the covariance needs d' <= 8 axes after dropping extent-1
      * axes (first moments: d' <= 32), and fewer than 2^32 counter rows. */
     TRIOT_OP_MOMENTS = 4,
@@ -148,9 +149,9 @@ typedef struct triot_moments_adj_params {
  *   params         host pointer to the op's params struct (or NULL).
  *   out            device pointer for ops with a reduced result (MOMENTS).
  *   workspace      device scratch of at least triot_workspace_size() bytes
- *                  for ops that need one (MOMENTS), zero-filled before its
- *                  first use; the library leaves it ready for the next call.
- *                  Calls that share a workspace must not overlap in time.
+ *                  for ops that need one (MOMENTS: per-workgroup partial
+ *                  sums); its contents need no initialisation.  Calls that
+ *                  share a workspace must not overlap in time.
  *   stream         HIP stream to enqueue on.
  * Returns TRIOT_OK or an error; on error nothing is enqueued. */
 triot_status triot_apply(triot_op op, int n_tensors, int d, const int64_t *shapes,
@@ -192,6 +193,13 @@ void triot_batch_destroy(triot_batch *handle);
  * params as in triot_apply (shared by all items). */
 triot_status triot_apply_batched(triot_op op, int n_items, const triot_item *items,
                                  const void *params, triot_batch *handle, hipStream_t stream);
+
+/* Replay the batch last planned by triot_apply_batched on `stream`, without
+ * re-validating the items: for serving loops that call the same batch
+ * (same shapes, pointers and op) again and again.  The caller guarantees
+ * that the buffers are still allocated.  TRIOT_E_INVALID if nothing was
+ * planned on this handle yet. */
+triot_status triot_batch_launch(triot_batch *handle, hipStream_t stream);
 
 /* Launch statistics of the last batched call: units (tiles) in the work
  * table, blocks of the persistent launch, and whether the call replayed
@@ -243,6 +251,7 @@ typedef struct triot_plan_info {
     int blocks;              /* workgroups of the launch */
     int threads;             /* threads per workgroup */
     int unroll;              /* elements per thread per step */
+    int inner_unit;          /* 1 when every operand is contiguous on the inner axis */
 } triot_plan_info;
 
 triot_status triot_plan_describe(triot_op op, int n_tensors, int d, const int64_t *shapes,

@@ -52,7 +52,8 @@ class PlanInfo(ctypes.Structure):
                 ("extents", ctypes.c_int64 * MAX_D), ("vec", ctypes.c_int),
                 ("high_axes", ctypes.c_int), ("low_axes", ctypes.c_int),
                 ("box_rows", ctypes.c_int64), ("units", ctypes.c_int64),
-                ("blocks", ctypes.c_int), ("threads", ctypes.c_int), ("unroll", ctypes.c_int)]
+                ("blocks", ctypes.c_int), ("threads", ctypes.c_int), ("unroll", ctypes.c_int),
+                ("inner_unit", ctypes.c_int)]
 
 
 class TriotError(RuntimeError):
@@ -65,7 +66,7 @@ class TriotError(RuntimeError):
 _lib = None
 
 EXPORTS = ["triot_apply", "triot_workspace_size", "triot_batch_create", "triot_batch_destroy",
-           "triot_apply_batched", "triot_batch_info", "triot_autotune", "triot_tune_reset",
+           "triot_apply_batched", "triot_batch_launch", "triot_batch_info", "triot_autotune", "triot_tune_reset",
            "triot_status_string", "triot_divmod_magic", "triot_plan_describe"]
 
 
@@ -91,6 +92,8 @@ def lib():
     L.triot_batch_destroy.argtypes = [P]
     L.triot_apply_batched.restype = I
     L.triot_apply_batched.argtypes = [I, I, ctypes.POINTER(Item), P, P, P]
+    L.triot_batch_launch.restype = I
+    L.triot_batch_launch.argtypes = [P, P]
     L.triot_batch_info.restype = I
     L.triot_batch_info.argtypes = [P, pI64, ctypes.POINTER(I), ctypes.POINTER(I)]
     L.triot_autotune.restype = I
@@ -215,6 +218,10 @@ def triot_apply_batched(op, items, params, handle, stream) -> int:
                                    ctypes.c_void_p(int(stream) if stream else 0))
     del keep
     return st
+
+
+def triot_batch_launch(handle, stream) -> int:
+    return lib().triot_batch_launch(handle, ctypes.c_void_p(int(stream) if stream else 0))
 
 
 def triot_batch_info(handle):

@@ -259,6 +259,12 @@ class Batch:
         st = L.triot_apply_batched(op, marshalled, params, self._h, _stream(dev))
         _check(st, "apply_batched")
 
+    def launch(self, device=None):
+        """Replay the last planned batch on the current stream (no
+        re-validation: the caller keeps the same buffers alive)."""
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        _check(L.triot_batch_launch(self._h, _stream(dev)), "batch_launch")
+
     def info(self):
         st, units, blocks, replayed = L.triot_batch_info(self._h)
         _check(st, "batch_info")
@@ -287,4 +293,22 @@ def describe(op, shapes, counter=None, ptrs=None, bases=None, params=None):
             "extents": [info.extents[i] for i in range(info.dims)], "vec": info.vec,
             "high_axes": info.high_axes, "low_axes": info.low_axes, "box_rows": info.box_rows,
             "units": info.units, "blocks": info.blocks, "threads": info.threads,
-            "unroll": info.unroll}
+            "unroll": info.unroll, "inner_unit": info.inner_unit}
+
+
+_CO_OP = {0: 0, 1: 1, 2: 2, 3: 3, 6: 4, 7: 5}   # public op -> kernel template op
+
+
+def kernel_name(op, plan):
+    """The demangled name of the kernel instance a plan launches (as the
+    profiler reports it)."""
+    if plan["kernel"] == 1:
+        cov = "true" if plan.get("cov") else "false"
+        dmax = 8 if plan["dims"] <= 8 else 32
+        base = "moments_kernel" if op == L.OP_MOMENTS else "moments_adj_kernel"
+        return "void triot::%s<%d, %s>(triot::SegPlan)" % (base, dmax, cov)
+    rows1 = "true" if plan["box_rows"] == 1 else "false"
+    unit = "true" if plan["inner_unit"] else "false"
+    u = 4 if op == L.OP_INDEX else plan["unroll"]
+    return "void triot::coiter_kernel<%d, %d, %d, %s, %s>(triot::CoPlan)" % (
+        _CO_OP[op], plan["vec"], u, rows1, unit)

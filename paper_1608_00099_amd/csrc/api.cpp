@@ -151,18 +151,18 @@ extern "C" size_t triot_workspace_size(triot_op op, int n_tensors, int d, const 
     Request r;
     if (validate(op, n_tensors, d, shapes, counter_shape, dummy, nullptr, nullptr, &r) != TRIOT_OK)
         return 0;
-    // The covariance tier is the larger one; size for it.
+    // Enough for either tier (first moments only, or with the covariance).
     triot_moments_params mp;
-    mp.flags = TRIOT_MOMENTS_FIRST | TRIOT_MOMENTS_COV;
     mp.out64 = nullptr;
     r.params = &mp;
-    SegLaunch L;
-    if (plan_segment(r, device_cus(), &L) != TRIOT_OK) {
-        mp.flags = TRIOT_MOMENTS_FIRST;
-        if (plan_segment(r, device_cus(), &L) != TRIOT_OK)
-            return 0;
+    size_t need = 0;
+    for (int flags : {TRIOT_MOMENTS_FIRST, TRIOT_MOMENTS_FIRST | TRIOT_MOMENTS_COV}) {
+        mp.flags = flags;
+        SegLaunch L;
+        if (plan_segment(r, device_cus(), &L) == TRIOT_OK)
+            need = std::max(need, segment_workspace_bytes(L));
     }
-    return segment_workspace_bytes(L);
+    return need;
 }
 
 extern "C" const char *triot_status_string(triot_status s)
@@ -229,10 +229,9 @@ extern "C" triot_status triot_plan_describe(triot_op op, int n_tensors, int d, c
         return st;
     const CoPlan &P = L.plan;
     info->kernel = 0;
-    info->dims = (int)P.D;
-    for (int i = 0; i < (int)P.D - 1; ++i)
-        info->extents[i] = P.ax[i].c;
-    info->extents[P.D - 1] = (int64_t)P.L * P.vec;
+    info->dims = L.dims;
+    for (int i = 0; i < L.dims; ++i)
+        info->extents[i] = L.extents[i];
     info->vec = (int)P.vec;
     info->high_axes = (int)P.nhigh;
     info->low_axes = (int)P.nlow;
@@ -241,6 +240,7 @@ extern "C" triot_status triot_plan_describe(triot_op op, int n_tensors, int d, c
     info->blocks = L.blocks;
     info->threads = NT;
     info->unroll = L.unroll;
+    info->inner_unit = L.unit ? 1 : 0;
     return TRIOT_OK;
 }
 
@@ -414,6 +414,21 @@ extern "C" triot_status triot_batch_info(const triot_batch *handle, int64_t *n_u
     if (replayed)
         *replayed = handle->replayed;
     return TRIOT_OK;
+}
+
+extern "C" triot_status triot_batch_launch(triot_batch *handle, hipStream_t stream)
+{
+    if (!handle)
+        return TRIOT_E_INVALID;
+    if (handle->units == 0 && handle->device >= 0)
+        return TRIOT_OK;  // a planned batch with no points
+    if (!handle->exec)
+        return TRIOT_E_INVALID;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != handle->device)
+        return TRIOT_E_INVALID;
+    handle->replayed = 1;
+    return to_status(hipGraphLaunch(handle->exec, stream));
 }
 
 extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const triot_item *items,

@@ -15,7 +15,7 @@ constexpr int MAXD = TRIOT_MAX_D;
 constexpr int MAXT = TRIOT_MAX_TENSORS;
 constexpr uint32_t NOBOUND = 0xFFFFFFFFu;
 constexpr int NT = 256;           // threads per workgroup (4 wave64)
-constexpr int RB_MAX = 256;       // LDS row-table capacity (rows per box)
+constexpr int RB_MAX = 1024;      // LDS row-table capacity (rows per box)
 constexpr int SEG_MAX = 32;       // per-thread segment length of the row kernels
 constexpr int MOM_TERMS_MAX = 1 + MAXD + 8 * 9 / 2;  // covariance limited to 8 axes
 
@@ -63,7 +63,16 @@ struct CoPlan {
     uint32_t esz;        // bytes per vector element (4 * vec)
     uint32_t vec;
     uint32_t unit;       // 1 when every inner stride is 1
-    uint32_t pad0;
+    // Split axis: the outermost low axis may be the lower part (m digits)
+    // of a counter axis of extent `sc` whose upper part (ceil(sc/m) blocks)
+    // is the innermost high axis.  The last block covers sc - hi*m < m
+    // digits, a prefix of the box; window bounds on that axis become a
+    // per-box limit on the low digit (stored in the row mask word).
+    uint32_t split;      // 0 or 1
+    uint32_t sm;         // digits per block (m)
+    uint32_t sc;         // true extent of the split axis
+    uint32_t rows_below; // box rows per low digit of the split axis
+    uint32_t sbound[MAXT];            // window extent on the split axis (NOBOUND = none)
     AxisDiv ax[MAXD];                 // outer axes, outermost first
     int64_t stride[MAXT][MAXD];       // outer strides per operand (vector units)
     uint32_t bound[MAXT][MAXD];       // window extent per outer axis (NOBOUND = unchecked)
@@ -72,6 +81,7 @@ struct CoPlan {
     int64_t base[MAXT];               // vector units
     uint64_t ptr[MAXT];               // device byte addresses
     uint64_t npoints;                 // counter points (INDEX output leading dimension)
+    uint64_t cstride[MAXD];           // counter flat stride of each high axis (INDEX)
 };
 
 // ---------------------------------------------------------------------

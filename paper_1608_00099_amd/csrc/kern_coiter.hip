@@ -38,6 +38,21 @@ __device__ __forceinline__ uint32_t logical_block()
     return b;
 }
 
+// Global-address-space pointers: loads and stores then address memory as a
+// uniform 64-bit base (scalar registers) plus a 32-bit per-lane offset.
+#define GLOBAL __attribute__((address_space(1)))
+typedef GLOBAL char gchar;
+
+template <class T> __device__ __forceinline__ T gload(const gchar *p, uint32_t off)
+{
+    return *(const GLOBAL T *)(p + off);
+}
+
+template <class T> __device__ __forceinline__ void gstore(gchar *p, uint32_t off, T v)
+{
+    *(GLOBAL T *)(p + off) = v;
+}
+
 template <int V> struct Vec;
 template <> struct Vec<1> {
     typedef uint32_t U;
@@ -54,7 +69,8 @@ template <> struct Vec<4> {
 
 struct RowTable {
     uint32_t off[MAXT][RB_MAX];   // pre-adjusted byte offsets of each box row
-    uint32_t mask[RB_MAX];        // bit k: the row lies inside operand k's window
+    uint32_t mask[RB_MAX];        // bits 0-7: the row lies inside operand k's window;
+                                  // bits 8-31: the row's digit on the split axis
 };
 
 // Tabulate the box rows: decode each row over the low axes and store, per
@@ -68,13 +84,18 @@ __device__ void fill_table(const CoPlan &P, RowTable &T)
 #pragma unroll
         for (int k = 0; k < MAXT; ++k)
             rel[k] = 0;
-        uint32_t mask = 0xFFFFFFFFu;
+        uint32_t mask = 0xFFu;
         uint32_t q = r;
+        uint32_t t = 0;
         for (int j = (int)(nhigh + nlow) - 1; j >= (int)nhigh; --j) {
             const AxisDiv a = P.ax[j];
-            uint32_t qq = div_u32(q, a);
-            uint32_t t = q - qq * a.c;
-            q = qq;
+            if (j == (int)nhigh) {
+                t = q;                       // outermost low axis: the rest
+            } else {
+                uint32_t qq = div_u32(q, a);
+                t = q - qq * a.c;
+                q = qq;
+            }
 #pragma unroll
             for (int k = 0; k < MAXT; ++k) {
                 if (k < (int)n) {
@@ -88,7 +109,8 @@ __device__ void fill_table(const CoPlan &P, RowTable &T)
         for (int k = 0; k < MAXT; ++k)
             if (k < (int)n)
                 T.off[k][r] = (rel[k] - r * P.L * P.istride[k]) * P.esz;
-        T.mask[r] = mask;
+        // t now holds the outermost low digit (the split axis' digit if split)
+        T.mask[r] = mask | (t << 8);
     }
 }
 
@@ -123,6 +145,8 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
     for (int k = 0; k < N; ++k)
         bb[k] = (k < (int)n) ? P.base[k] : 0;
     uint32_t himask = 0xFFFFFFFFu;
+    uint32_t blk = 0;          // block digit of the split axis
+    uint64_t fbase = 0;        // counter flat index of the box start (INDEX)
     {
         uint32_t q = box;
         for (int i = (int)P.nhigh - 1; i >= 0; --i) {
@@ -135,6 +159,10 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                 t = q - qq * a.c;
                 q = qq;
             }
+            if (i == (int)P.nhigh - 1)
+                blk = t;
+            if (OP == CO_INDEX)
+                fbase += (uint64_t)t * P.cstride[i];
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 if (k < (int)n) {
@@ -145,20 +173,39 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
             }
         }
     }
+    uint32_t bev = P.BE;       // elements of this box (a prefix when split)
+    uint32_t lolim[N];         // per operand: limit on the split digit
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        lolim[k] = 0xFFFFFFFFu;
+    if (P.split) {
+        const uint32_t first = blk * P.sm;
+        const uint32_t rows = min(P.sm, P.sc - first);
+        bev = rows * P.rows_below * P.L;
+        if (OpInfo<OP>::PRED) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const uint32_t b = P.sbound[k < (int)n ? k : 0];
+                lolim[k] = (b == NOBOUND) ? 0xFFFFFFFFu : (b > first ? b - first : 0u);
+            }
+        }
+    }
     const uint32_t e0 = part * P.PE;
-    const uint32_t e1 = min(e0 + P.PE, P.BE);
+    const uint32_t e1 = min(e0 + P.PE, bev);
+    if (e0 >= e1)
+        return;
     if (ROWS1) {
 #pragma unroll
         for (int k = 0; k < N; ++k)
             if (k < (int)n)
                 bb[k] += (int64_t)e0 * P.istride[k];
     }
-    const uint32_t esz = P.esz;
-    char *bp[N];
+    constexpr uint32_t esz = 4u * V;   // == P.esz: the launcher picks V = P.vec
+    gchar *bp[N];
     uint32_t isb[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        bp[k] = (char *)(uintptr_t)(P.ptr[k < (int)n ? k : 0]) + bb[k] * (int64_t)esz;
+        bp[k] = (gchar *)(uintptr_t)(P.ptr[k < (int)n ? k : 0]) + bb[k] * (int64_t)esz;
         isb[k] = UNIT ? esz : P.istride[k < (int)n ? k : 0] * esz;
     }
 
@@ -186,10 +233,12 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
             jj[u] = j;
             pm[u] = 0xFFFFFFFFu;
             if (OpInfo<OP>::PRED) {
-                uint32_t m = himask & (ROWS1 ? 0xFFFFFFFFu : T.mask[row]);
+                const uint32_t rm = ROWS1 ? 0xFFu : T.mask[row];
+                const uint32_t dig = rm >> 8;
+                uint32_t m = himask & rm & 0xFFu;
 #pragma unroll
                 for (int k = 0; k < N; ++k)
-                    if (j >= P.ibound[k])
+                    if (j >= P.ibound[k] || dig >= lolim[k])
                         m &= ~(1u << k);
                 pm[u] = m;
             }
@@ -208,50 +257,50 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u])
-                    v[u] = *(const VU *)(bp[1] + off[1][u]);
+                    v[u] = gload<VU>(bp[1], off[1][u]);
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u])
-                    *(VU *)(bp[0] + off[0][u]) = v[u];
+                    gstore<VU>(bp[0], off[0][u], v[u]);
         } else if constexpr (OP == CO_FILL) {
             VU v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 v[u] = (VU)0u;
                 if (valid[u] && (pm[u] & 2u))
-                    v[u] = *(const VU *)(bp[1] + off[1][u]);
+                    v[u] = gload<VU>(bp[1], off[1][u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u])
-                    *(VU *)(bp[0] + off[0][u]) = v[u];
+                    gstore<VU>(bp[0], off[0][u], v[u]);
         } else if constexpr (OP == CO_MUL_ACC) {
             VF x[U], y[U], z[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u]) {
-                    x[u] = *(const VF *)(bp[0] + off[0][u]);
-                    y[u] = *(const VF *)(bp[1] + off[1][u]);
-                    z[u] = *(const VF *)(bp[2] + off[2][u]);
+                    x[u] = gload<VF>(bp[0], off[0][u]);
+                    y[u] = gload<VF>(bp[1], off[1][u]);
+                    z[u] = gload<VF>(bp[2], off[2][u]);
                 }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u]) {
                     VF prod = y[u] * z[u];       // rounded once (no contraction)
-                    *(VF *)(bp[0] + off[0][u]) = x[u] + prod;
+                    gstore<VF>(bp[0], off[0][u], x[u] + prod);
                 }
         } else if constexpr (OP == CO_MUL) {
             VF a[U], b[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u]) {
-                    a[u] = *(const VF *)(bp[1] + off[1][u]);
-                    b[u] = *(const VF *)(bp[2] + off[2][u]);
+                    a[u] = gload<VF>(bp[1], off[1][u]);
+                    b[u] = gload<VF>(bp[2], off[2][u]);
                 }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u])
-                    *(VF *)(bp[0] + off[0][u]) = a[u] * b[u];
+                    gstore<VF>(bp[0], off[0][u], a[u] * b[u]);
         } else if constexpr (OP == CO_MUL_ADJ) {
             // operands: 0 ga, 1 gb, 2 gout, 3 a, 4 b
             VF g[U], a[U], b[U];
@@ -262,11 +311,11 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                 b[u] = (VF)0.0f;
                 const bool inI = valid[u] && (pm[u] & 4u);
                 if (inI) {
-                    g[u] = *(const VF *)(bp[2] + off[2][u]);
+                    g[u] = gload<VF>(bp[2], off[2][u]);
                     if (pm[u] & 2u)
-                        a[u] = *(const VF *)(bp[3] + off[3][u]);
+                        a[u] = gload<VF>(bp[3], off[3][u]);
                     if (pm[u] & 1u)
-                        b[u] = *(const VF *)(bp[4] + off[4][u]);
+                        b[u] = gload<VF>(bp[4], off[4][u]);
                 }
             }
 #pragma unroll
@@ -275,9 +324,9 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                     continue;
                 const bool inI = (pm[u] & 4u) != 0;
                 if (pm[u] & 1u)
-                    *(VF *)(bp[0] + off[0][u]) = inI ? g[u] * b[u] : (VF)0.0f;
+                    gstore<VF>(bp[0], off[0][u], inI ? g[u] * b[u] : (VF)0.0f);
                 if (pm[u] & 2u)
-                    *(VF *)(bp[1] + off[1][u]) = inI ? g[u] * a[u] : (VF)0.0f;
+                    gstore<VF>(bp[1], off[1][u], inI ? g[u] * a[u] : (VF)0.0f);
             }
         } else if constexpr (OP == CO_INDEX) {
             // Element offsets (base included) of every operand, row-major
@@ -287,7 +336,7 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
             for (int u = 0; u < U; ++u) {
                 if (!valid[u])
                     continue;
-                uint64_t f = (uint64_t)box * P.BE + ev[u];
+                uint64_t f = fbase + ev[u];
 #pragma unroll
                 for (int k = 0; k < N; ++k)
                     if (k < (int)n)
@@ -340,21 +389,33 @@ __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ 
         else
             hi = mid;
     }
+    // The current item's plan lives in LDS (one coalesced copy per item), so
+    // the per-unit decode never waits on global memory.
+    __shared__ CoPlan Ps;
     uint32_t item = lo;
-    uint32_t cur = 0xFFFFFFFFu;
+    uint32_t first = ustart[item], next = ustart[item + 1];
+    bool loaded = false;
     for (uint32_t u = u0; u < u1; ++u) {
-        while (u >= ustart[item + 1])
-            ++item;
-        const CoPlan &P = plans[item];
-        const bool rows1 = P.RB == 1;
-        if (item != cur) {
+        if (u >= next || !loaded) {
+            while (u >= next) {
+                ++item;
+                first = next;
+                next = ustart[item + 1];
+            }
             __syncthreads();
-            if (!rows1)
-                fill_table(P, T);
+            const uint32_t *src = (const uint32_t *)(plans + item);
+            uint32_t *dst = (uint32_t *)&Ps;
+            for (uint32_t i = threadIdx.x; i < sizeof(CoPlan) / 4; i += NT)
+                dst[i] = src[i];
             __syncthreads();
-            cur = item;
+            if (Ps.RB > 1)
+                fill_table(Ps, T);
+            __syncthreads();
+            loaded = true;
         }
-        const uint32_t lu = u - ustart[item];
+        const CoPlan &P = Ps;
+        const bool rows1 = P.RB == 1;
+        const uint32_t lu = u - first;
         if (rows1) {
             if (P.unit)
                 run_unit<OP, 1, U, true, true>(P, lu, T);

@@ -15,10 +15,12 @@
 //
 // Partial sums are float64 per thread (on CDNA the float64 FMA issues at the
 // same rate as an unpacked float32 FMA), reduced across the wave with
-// shuffles, across the workgroup through LDS, and across workgroups by the
-// last workgroup to finish (a ticket counter), which adds the per-workgroup
-// partials in fixed order with TwoSum compensation.  No float atomics: the
-// result is deterministic.
+// shuffles, across the workgroup through LDS, and across workgroups by a
+// second, one-workgroup kernel that adds the per-workgroup partials in fixed
+// order with TwoSum compensation.  No float atomics: the result is
+// deterministic.  Ordering that combine behind the first kernel by the
+// stream, rather than by a device-scope fence in every workgroup (which on
+// CDNA writes back the whole L2 of the XCD), costs one short launch.
 //
 // Accumulator positions: p = 0 is the inner axis (D-1), p >= 1 the outer
 // axis D-1-p, so that register arrays are indexed by compile-time positions.
@@ -42,6 +44,8 @@ __device__ __forceinline__ uint32_t seg_logical_block()
         return (b & 7u) * (g >> 3) + (b >> 3);
     return b;
 }
+
+#define GLOBAL __attribute__((address_space(1)))
 
 // LDS staging: one padding word every 32 words keeps the per-thread segment
 // reads (stride L words across lanes) spread over the banks.
@@ -128,16 +132,6 @@ __device__ __forceinline__ int64_t row_offset(const SegPlan &P, int k, const uin
     return off;
 }
 
-__device__ __forceinline__ float load_weight(const SegPlan &P, uint64_t flat)
-{
-    float w = ((const float *)(uintptr_t)P.ptr[0])[P.base[0] + (int64_t)flat];
-#pragma unroll
-    for (int k = 1; k < 4; ++k)
-        if (k < (int)P.n)
-            w *= ((const float *)(uintptr_t)P.ptr[k])[P.base[k] + (int64_t)flat];
-    return w;
-}
-
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -161,9 +155,6 @@ __global__ __launch_bounds__(NT) void moments_kernel(const SegPlan P)
     constexpr int T = TT::T;
     __shared__ float stage[STAGE_WORDS];
     __shared__ double red[NT / 64][T];
-    __shared__ double tot[T];
-    __shared__ int pos_of[MAXD];
-    __shared__ uint32_t is_last;
 
     double acc[T];
 #pragma unroll
@@ -177,18 +168,74 @@ __global__ __launch_bounds__(NT) void moments_kernel(const SegPlan P)
     const uint64_t t0 = (lb * P.ntiles) / g;
     const uint64_t t1 = ((lb + 1) * P.ntiles) / g;
 
-    for (uint64_t tile = t0; tile < t1; ++tile) {
-        const uint64_t s0 = tile * NT;
-        const uint32_t nsg = (uint32_t)min((uint64_t)NT, P.nseg - s0);
+    // Tile geometry: NT consecutive segments, a contiguous range of nel
+    // counter points starting at flat index f0.
+    auto geom = [&](uint64_t tile, uint64_t &s0, uint32_t &nsg, uint64_t &f0, uint32_t &nel) {
+        s0 = tile * NT;
+        nsg = (uint32_t)min((uint64_t)NT, P.nseg - s0);
         const Seg first = seg_of(P, s0);
         const Seg last = seg_of(P, s0 + nsg - 1);
-        const uint64_t f0 = seg_start(P, first);
-        const uint32_t nel = (uint32_t)(seg_start(P, last) + last.len - f0);
+        f0 = seg_start(P, first);
+        nel = (uint32_t)(seg_start(P, last) + last.len - f0);
+    };
+    // Software pipeline for contiguous operands: the weights of the next
+    // tile are loaded into registers (groups of 8 independent loads, indices
+    // clamped into the tile so that no load sits behind a branch) while the
+    // current tile is folded from LDS.
+    constexpr int PRE = SEG_MAX;  // words per thread per tile (nel <= NT * SEG_MAX)
+    float pre[PRE];
+    auto load_tile = [&](uint64_t f0, uint32_t nel) {
+#pragma unroll
+        for (int gq = 0; gq < PRE / 8; ++gq) {
+            if ((uint32_t)(gq * 8 * NT) < nel) {
+                uint32_t ec[8];
+                const GLOBAL float *w0 = (const GLOBAL float *)(uintptr_t)P.ptr[0] + P.base[0] + f0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    ec[u] = min(threadIdx.x + (uint32_t)((gq * 8 + u) * NT), nel - 1);
+                    pre[gq * 8 + u] = w0[ec[u]];
+                }
+                if (P.n > 1) {
+#pragma unroll
+                    for (int k = 1; k < 4; ++k) {
+                        if (k < (int)P.n) {
+                            const GLOBAL float *wk =
+                                (const GLOBAL float *)(uintptr_t)P.ptr[k] + P.base[k] + f0;
+#pragma unroll
+                            for (int u = 0; u < 8; ++u)
+                                pre[gq * 8 + u] *= wk[ec[u]];
+                        }
+                    }
+                }
+            }
+        }
+    };
+    if (P.full && t0 < t1) {
+        uint64_t s0, f0;
+        uint32_t nsg, nel;
+        geom(t0, s0, nsg, f0, nel);
+        load_tile(f0, nel);
+    }
+
+    for (uint64_t tile = t0; tile < t1; ++tile) {
+        uint64_t s0, f0;
+        uint32_t nsg, nel;
+        geom(tile, s0, nsg, f0, nel);
         if (P.full) {
+            __syncthreads();               // the previous tile's reads are done
+#pragma unroll
+            for (int i = 0; i < PRE; ++i) {
+                const uint32_t e = threadIdx.x + (uint32_t)(i * NT);
+                if (e < nel)
+                    stage[sidx(e)] = pre[i];
+            }
             __syncthreads();
-            for (uint32_t e = threadIdx.x; e < nel; e += NT)
-                stage[sidx(e)] = load_weight(P, f0 + e);
-            __syncthreads();
+            if (tile + 1 < t1) {
+                uint64_t s0n, f0n;
+                uint32_t nsgn, neln;
+                geom(tile + 1, s0n, nsgn, f0n, neln);
+                load_tile(f0n, neln);      // in flight during the fold below
+            }
         }
         if (threadIdx.x < nsg) {
             const Seg sg = seg_of(P, s0 + threadIdx.x);
@@ -258,33 +305,97 @@ __global__ __launch_bounds__(NT) void moments_kernel(const SegPlan P)
             red[wave][i] = v;
     }
     __syncthreads();
+    // Partials are term-major (term i of block b at i * nblocks + b) so the
+    // combining workgroup reads them with coalesced loads.
     double *partials = (double *)((char *)(uintptr_t)P.ws + 256);
+    const uint32_t nb = P.nblocks;
     for (int i = threadIdx.x; i < T; i += NT) {
         double v = red[0][i];
 #pragma unroll
         for (int w = 1; w < NT / 64; ++w)
             v += red[w][i];
-        partials[(size_t)blockIdx.x * T + i] = v;
+        partials[(size_t)i * nb + blockIdx.x] = v;
     }
-    // ---- last workgroup combines all partials ----
-    __threadfence();
-    __syncthreads();
-    unsigned int *ticket = (unsigned int *)(uintptr_t)P.ws;
-    if (threadIdx.x == 0) {
-        unsigned int old = atomicAdd(ticket, 1u);
-        is_last = (old == P.nblocks - 1) ? 1u : 0u;
+}
+
+// Combines the per-workgroup partials of moments_kernel (one workgroup,
+// launched right after it on the same stream: the kernel boundary makes
+// every partial visible without a device-wide cache write-back per block)
+// and writes [M, E, C] in the caller's layout.
+template <int DMAX, bool COV>
+__global__ __launch_bounds__(NT) void moments_final_kernel(const SegPlan P)
+{
+    typedef Terms<DMAX, COV> TT;
+    constexpr int T = TT::T;
+    __shared__ double red[NT / 64][T];
+    __shared__ double rc[NT / 64][T];
+    __shared__ double tot[T];
+    __shared__ int pos_of[MAXD];
+    const int D = (int)P.D;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double *partials = (const double *)((const char *)(uintptr_t)P.ws + 256);
+    const uint32_t nb = P.nblocks;
+    // Every thread folds blocks tid, tid + NT, ... of every term into a
+    // compensated (sum, error) pair; the pairs then meet in a fixed tree:
+    // lanes by xor-shuffles, waves in index order.  Deterministic.
+    constexpr int CH = 8;  // terms reduced together (bounds the registers)
+    constexpr int TP = (T + CH - 1) / CH * CH;  // workspace rows (padded)
+#pragma unroll
+    for (int i0 = 0; i0 < TP; i0 += CH) {
+        double ls[CH], lc[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            ls[q] = 0.0;
+            lc[q] = 0.0;
+        }
+        for (uint32_t b0 = 0; b0 < nb; b0 += NT) {
+            // unconditional loads (clamped block index), then a select
+            const uint32_t b = b0 + threadIdx.x;
+            const bool ok = b < nb;
+            const uint32_t bc = ok ? b : 0u;
+            double v[CH];
+#pragma unroll
+            for (int q = 0; q < CH; ++q)
+                v[q] = partials[(size_t)(i0 + q) * nb + bc];
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                double e;
+                two_sum(ls[q], ok ? v[q] : 0.0, ls[q], e);
+                lc[q] += e;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int i = i0 + q;
+            if (i >= T)
+                break;
+            double s = ls[q], c = lc[q];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double so = __shfl_xor(s, o, 64);
+                const double co = __shfl_xor(c, o, 64);
+                double e;
+                // (lower lane first) keeps both lanes of a pair bit-identical
+                if (lane & o)
+                    two_sum(so, s, s, e);
+                else
+                    two_sum(s, so, s, e);
+                c = (lane & o) ? (co + c) + e : (c + co) + e;
+            }
+            if (lane == 0) {
+                red[wave][i] = s;
+                rc[wave][i] = c;
+            }
+        }
     }
     __syncthreads();
-    if (!is_last)
-        return;
-    __threadfence();
     for (int i = threadIdx.x; i < T; i += NT) {
-        double s = 0.0, c = 0.0;
-        for (uint32_t b = 0; b < P.nblocks; ++b) {
-            const double v = partials[(size_t)b * T + i];
+        double s = red[0][i], c = rc[0][i];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) {
             double e;
-            two_sum(s, v, s, e);
-            c += e;
+            two_sum(s, red[w][i], s, e);
+            c = (c + rc[w][i]) + e;
         }
         tot[i] = s + c;
     }
@@ -334,8 +445,6 @@ __global__ __launch_bounds__(NT) void moments_kernel(const SegPlan P)
         if (out64)
             out64[o] = v;
     }
-    if (threadIdx.x == 0)
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------
@@ -473,7 +582,7 @@ __global__ __launch_bounds__(NT) void moments_adj_kernel(const SegPlan P)
         }
         if (P.full) {
             __syncthreads();
-            float *dst = gout + P.base[0] + (int64_t)f0;
+            GLOBAL float *dst = (GLOBAL float *)(uintptr_t)P.ptr[0] + P.base[0] + (int64_t)f0;
             for (uint32_t e = threadIdx.x; e < nel; e += NT)
                 dst[e] = stage[sidx(e)];
             __syncthreads();
@@ -488,10 +597,13 @@ hipError_t launch_moments(const SegLaunch &L, hipStream_t st)
     const bool cov = (L.plan.flags & TRIOT_MOMENTS_COV) != 0;
     if (cov) {
         hipLaunchKernelGGL((moments_kernel<8, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        hipLaunchKernelGGL((moments_final_kernel<8, true>), dim3(1), dim3(NT), 0, st, L.plan);
     } else if (L.dmax <= 8) {
         hipLaunchKernelGGL((moments_kernel<8, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        hipLaunchKernelGGL((moments_final_kernel<8, false>), dim3(1), dim3(NT), 0, st, L.plan);
     } else {
         hipLaunchKernelGGL((moments_kernel<32, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        hipLaunchKernelGGL((moments_final_kernel<32, false>), dim3(1), dim3(NT), 0, st, L.plan);
     }
     return hipGetLastError();
 }
@@ -507,6 +619,41 @@ hipError_t launch_moments_adj(const SegLaunch &L, hipStream_t st)
         hipLaunchKernelGGL((moments_adj_kernel<32, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
     }
     return hipGetLastError();
+}
+
+}  // namespace triot
+
+namespace triot {
+
+// Resident workgroups per CU of the row kernels (their register and LDS
+// needs differ by tier), asked of the runtime once; 2 when no device answers.
+int segment_blocks_per_cu(bool adj, bool cov, int dmax)
+{
+    static int cache[2][2][2] = {};
+    const int a = adj ? 1 : 0, c = cov ? 1 : 0, m = dmax > 8 ? 1 : 0;
+    if (!cache[a][c][m]) {
+        int nb = 0;
+        hipError_t e;
+        if (!adj) {
+            if (cov)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_kernel<8, true>, NT, 0);
+            else if (dmax <= 8)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_kernel<8, false>, NT, 0);
+            else
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_kernel<32, false>, NT, 0);
+        } else {
+            if (cov)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_adj_kernel<8, true>, NT, 0);
+            else if (dmax <= 8)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_adj_kernel<8, false>, NT,
+                                                                 0);
+            else
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_adj_kernel<32, false>,
+                                                                 NT, 0);
+        }
+        cache[a][c][m] = (e == hipSuccess && nb > 0) ? nb : 2;
+    }
+    return cache[a][c][m];
 }
 
 }  // namespace triot

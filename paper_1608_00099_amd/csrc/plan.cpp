@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "launch.h"
+
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -466,37 +468,100 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
 
     // 5. Box: the fewest low axes whose rows reach the unit size, within the
     //    LDS table, the exact range of the row magic and 31-bit offsets.
+    //    If the box is still short of a unit, the next axis is split: its
+    //    lower m digits join the box, its blocks of m digits become a high
+    //    axis (the last block being a shorter prefix of the box).
     const int nouter = D - 1;
-    int nlow = 0;
+    const int rb_cap = std::max(1, std::min(s.rb_max, RB_MAX));
+    // Does a box of the full low axes [first, nouter) plus mm digits of
+    // axis `split_axis` (or none) satisfy the magic and offset limits?
+    auto fits = [&](int first, int split_axis, int64_t mm, int64_t rows) -> bool {
+        if ((unsigned __int128)rows * L * L > ((unsigned __int128)1 << 32))
+            return false;
+        for (int k = 0; k < n; ++k) {
+            int64_t span = (L - 1) * is[k];
+            for (int j = first; j < nouter; ++j)
+                span += (m[j].c - 1) * (m[j].S[k] / vec);
+            if (split_axis >= 0)
+                span += (mm - 1) * (m[split_axis].S[k] / vec);
+            if ((span + 1) * (int64_t)esz >= (int64_t(1) << 31))
+                return false;
+        }
+        return true;
+    };
+    int nfull = 0;
     int64_t RB = 1;
-    int rb_cap = std::max(1, std::min(s.rb_max, RB_MAX));
     for (int i = nouter - 1; i >= 0; --i) {
         if (RB * L >= s.pe_target)
             break;
         int64_t rb2 = RB * m[i].c;
-        if (rb2 > rb_cap)
-            break;
-        if ((unsigned __int128)rb2 * L * L > ((unsigned __int128)1 << 32))
-            break;
-        bool ok = true;
-        for (int k = 0; k < n && ok; ++k) {
-            int64_t span = (L - 1) * is[k];
-            for (int j = i; j < nouter; ++j)
-                span += (m[j].c - 1) * (m[j].S[k] / vec);
-            if ((span + 1) * (int64_t)esz >= (int64_t(1) << 31))
-                ok = false;
-        }
-        if (!ok)
+        if (rb2 > rb_cap || !fits(i, -1, 1, rb2))
             break;
         RB = rb2;
-        nlow++;
+        nfull++;
     }
-    const int nhigh = nouter - nlow;
+    const int a = nouter - 1 - nfull;  // next axis, candidate for the split
+    int64_t mm = 1;
+    if (a >= 0 && RB * L < s.pe_target) {
+        int64_t want = (s.pe_target + RB * L - 1) / (RB * L);
+        mm = std::min<int64_t>({m[a].c - 1, want, (int64_t)rb_cap / RB});
+        while (mm >= 2 && !fits(a + 1, a, mm, RB * mm))
+            mm /= 2;
+    }
+    const bool split = mm >= 2;
+    const int64_t rows_below = RB;
+    if (split)
+        RB *= mm;
+
+    // Outer axes of the kernel: [0, a) unchanged, then (split) the block
+    // axis and the digit axis, then the full low axes.
+    struct KAx {
+        int64_t c;
+        int64_t S[MAXT];
+        int64_t B[MAXT];
+    };
+    KAx kx[MAXD + 1];
+    int nk = 0;
+    const int first_low = split ? a : a + 1;
+    for (int i = 0; i < first_low; ++i) {
+        kx[nk].c = m[i].c;
+        for (int k = 0; k < n; ++k) {
+            kx[nk].S[k] = m[i].S[k];
+            kx[nk].B[k] = m[i].B[k];
+        }
+        nk++;
+    }
+    if (split) {
+        KAx hi, lo;
+        hi.c = (m[a].c + mm - 1) / mm;
+        lo.c = mm;
+        for (int k = 0; k < n; ++k) {
+            hi.S[k] = m[a].S[k] * mm;
+            lo.S[k] = m[a].S[k];
+            hi.B[k] = -1;   // the split axis' window bound is applied per box
+            lo.B[k] = -1;
+        }
+        kx[nk++] = hi;
+        kx[nk++] = lo;
+    }
+    for (int i = a + 1; i < nouter; ++i) {
+        kx[nk].c = m[i].c;
+        for (int k = 0; k < n; ++k) {
+            kx[nk].S[k] = m[i].S[k];
+            kx[nk].B[k] = m[i].B[k];
+        }
+        nk++;
+    }
+    const int nlow = nfull + (split ? 1 : 0);
+    const int nhigh = nk - nlow;
     int64_t nboxes = 1;
     for (int i = 0; i < nhigh; ++i)
-        nboxes *= m[i].c;
+        nboxes *= kx[i].c;
     if (nboxes >= (int64_t(1) << 32))
         return TRIOT_E_UNSUPPORTED;
+    for (int i = 0; i < nk; ++i)
+        if (kx[i].c >= (int64_t(1) << 32))
+            return TRIOT_E_UNSUPPORTED;
 
     int64_t BE = RB * L;
     int64_t pe_cap = s.pe_target;
@@ -512,7 +577,7 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
         return TRIOT_E_UNSUPPORTED;
 
     // 6. The kernel argument.
-    P.D = (uint32_t)D;
+    P.D = (uint32_t)(nk + 1);
     P.n = (uint32_t)n;
     P.nhigh = (uint32_t)nhigh;
     P.nlow = (uint32_t)nlow;
@@ -530,17 +595,42 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     P.esz = esz;
     P.vec = (uint32_t)vec;
     P.unit = unit ? 1u : 0u;
+    P.split = split ? 1u : 0u;
+    P.sm = split ? (uint32_t)mm : 1u;
+    P.sc = split ? (uint32_t)m[a].c : 1u;
+    P.rows_below = (uint32_t)rows_below;
     uint32_t predmask = 0;
-    for (int i = 0; i < nouter; ++i) {
-        magic_for((uint32_t)m[i].c, &P.ax[i]);
+    for (int k = 0; k < n; ++k) {
+        P.sbound[k] = NOBOUND;
+        if (split && m[a].B[k] >= 0) {
+            P.sbound[k] = (uint32_t)m[a].B[k];
+            predmask |= 1u << k;
+        }
+    }
+    for (int i = 0; i < nk; ++i) {
+        if (kx[i].c >= 2)
+            magic_for((uint32_t)kx[i].c, &P.ax[i]);
+        else
+            P.ax[i] = trivial_div();
         for (int k = 0; k < n; ++k) {
-            P.stride[k][i] = m[i].S[k] / vec;
-            if (m[i].B[k] >= 0) {
-                P.bound[k][i] = (uint32_t)m[i].B[k];
+            P.stride[k][i] = kx[i].S[k] / vec;
+            if (kx[i].B[k] >= 0) {
+                P.bound[k][i] = (uint32_t)kx[i].B[k];
                 predmask |= 1u << k;
             } else {
                 P.bound[k][i] = NOBOUND;
             }
+        }
+    }
+    // Counter flat stride of each high axis (the INDEX output position).
+    {
+        int64_t below = BE;   // elements of one full box
+        for (int i = nhigh - 1; i >= 0; --i) {
+            P.cstride[i] = (uint64_t)below;
+            if (split && i == nhigh - 1)
+                below = (int64_t)m[a].c * rows_below * L;   // the true extent of the split axis
+            else
+                below *= kx[i].c;
         }
     }
     for (int k = 0; k < n; ++k) {
@@ -554,9 +644,11 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
         P.base[k] = base[k] / vec;
         P.ptr[k] = (uint64_t)(uintptr_t)r.ptr[k];
     }
-    // A predicated operand whose window is empty on some axis is never touched.
     P.predmask = predmask;
     P.npoints = (uint64_t)r.npoints;
+    out->dims = D;
+    for (int i = 0; i < D; ++i)
+        out->extents[i] = m[i].c;
 
     int blocks = (int)std::min<int64_t>(nunits, (int64_t)cus * std::max(1, s.blocks_per_cu));
     if (blocks > 8)
@@ -651,9 +743,13 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     // Accumulator slots of the kernel tier: M, DMAX first sums and, with
     // the covariance, DMAX(DMAX+1)/2 second sums (DMAX = 8 or 32).
     const int dmax = (D <= 8) ? 8 : 32;
-    P.nterms = (uint32_t)(1 + dmax + (cov ? dmax * (dmax + 1) / 2 : 0));
+    // Workspace rows per block: the slots, padded to a multiple of 8 (the
+    // final reduction reads them 8 at a time, unconditionally).
+    P.nterms = (uint32_t)((1 + dmax + (cov ? dmax * (dmax + 1) / 2 : 0) + 7) / 8 * 8);
 
-    int64_t blocks = std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * 4);
+    // Persistent grid: as many workgroups as can be resident at once.
+    const int bpc = segment_blocks_per_cu(r.op == TRIOT_OP_MOMENTS_ADJ, cov, dmax);
+    int64_t blocks = std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * bpc);
     if (blocks > 8)
         blocks = (blocks + 7) / 8 * 8;
     blocks = std::max<int64_t>(blocks, 1);
@@ -665,8 +761,7 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
 
 size_t segment_workspace_bytes(const SegLaunch &l)
 {
-    // Per-block partial sums (float64) after a 256-byte header holding the
-    // completion ticket.
+    // Per-workgroup partial sums (float64), after a 256-byte aligned header.
     return 256 + (size_t)l.plan.nblocks * l.plan.nterms * sizeof(double);
 }
 

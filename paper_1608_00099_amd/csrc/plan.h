@@ -36,6 +36,8 @@ struct Request {
 
 struct CoLaunch {
     CoPlan plan;
+    int dims;                 // the merged counter (before any split)
+    int64_t extents[MAXD];    // its extents, inner axis in elements
     int blocks;
     int unroll;
     bool rows1;     // RB == 1

@@ -150,7 +150,7 @@ def test_plan_box_split_limits():
     # very short rows: the box tabulates several low axes (bounded table)
     p = api.describe(L.OP_COPY, [(9, 5, 13, 21, 14, 6, 3, 25)] * 1 + [(10, 6, 14, 22, 15, 7, 4, 26)],
                      counter=(9, 5, 13, 21, 14, 6, 3, 25))
-    assert p["box_rows"] <= 256
+    assert p["box_rows"] <= 1024
     assert p["low_axes"] >= 1
     assert p["units"] >= p["blocks"]
     # one very long row: a single-row box split into units

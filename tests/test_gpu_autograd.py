@@ -1,0 +1,97 @@
+"""The differentiable pipeline at full size: pad (24,)^5 -> (32,)^5, product
+with a (28,30,32,26,32) weight over the intersection, E-based loss, forward
+and backward through torch.autograd with the library's adjoint kernels.
+
+The gradient is checked against the oracle's float64 analytic gradient
+(element by element) and against float64 central finite differences of the
+oracle pipeline (random unit directions and single coordinates), at relative
+error 1e-4."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import pipeline
+from paper_1608_00099_amd import api, autograd, inputs
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grad(x_np, w_np, lam):
+    x = torch.from_numpy(x_np).cuda().requires_grad_(True)
+    w = torch.from_numpy(w_np).cuda().requires_grad_(True)
+    lam_t = torch.from_numpy(lam.astype(np.float32)).cuda()
+    P = autograd.pad_embed(x, inputs.CFG5_P)
+    y = autograd.mul(P, w)
+    M, E, C = autograd.moments(y)
+    loss = (lam_t * E).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return (float(loss), x.grad.cpu().numpy().astype(np.float64).reshape(-1),
+            w.grad.cpu().numpy().astype(np.float64).reshape(-1))
+
+
+@pytest.mark.timeout(900)
+def test_pipeline_gradient_full_size():
+    announce("autograd cfg5")
+    x_np, w_np, lam = inputs.cfg5_values()
+    xs, ps, ws = inputs.CFG5_X, inputs.CFG5_P, inputs.CFG5_W
+    loss, gx, gw = _gpu_grad(x_np, w_np, lam)
+    x64 = x_np.astype(np.float64).reshape(-1)
+    w64 = w_np.astype(np.float64).reshape(-1)
+    L_ref = pipeline.loss(x64, w64, lam, xs, ps, ws)
+    assert abs(loss - L_ref) <= 1e-6 * max(1.0, abs(L_ref))
+    rx, rw = pipeline.gradient(x64, w64, lam, xs, ps, ws)
+    for g, r in ((gx, rx), (gw, rw)):
+        assert np.linalg.norm(g - r) <= 1e-4 * np.linalg.norm(r)
+        den = np.maximum(np.abs(r), 1e-3 * np.sqrt(np.mean(r * r)))
+        assert (np.abs(g - r) / den).max() <= 1e-4
+    # float64 central differences of the oracle pipeline
+    rng = np.random.default_rng(55)
+    for which, vec, grad in ((0, x64, gx), (1, w64, gw)):
+        for _ in range(3):
+            v = rng.standard_normal(vec.size)
+            v /= np.linalg.norm(v)
+            # The loss is a ratio of sums linear in x and w, so the central
+            # difference's truncation error is ~ h * |dM/dv| / M ~ 1e-7 h;
+            # a large step keeps the float64 summation noise of the two
+            # 22M-term loss evaluations (~1e-11 absolute) far below 1e-4.
+            h = 1.0
+            a = [x64, w64]
+            b = [x64, w64]
+            a[which] = vec + h * v
+            b[which] = vec - h * v
+            fd = (pipeline.loss(a[0], a[1], lam, xs, ps, ws) -
+                  pipeline.loss(b[0], b[1], lam, xs, ps, ws)) / (2 * h)
+            assert abs(float(np.dot(grad, v)) - fd) <= 1e-4 * abs(fd)
+        for k in rng.choice(vec.size, size=3, replace=False):
+            h = 0.25
+            a = [x64, w64]
+            b = [x64, w64]
+            a[which] = vec.copy()
+            b[which] = vec.copy()
+            a[which][k] += h
+            b[which][k] -= h
+            fd = (pipeline.loss(a[0], a[1], lam, xs, ps, ws) -
+                  pipeline.loss(b[0], b[1], lam, xs, ps, ws)) / (2 * h)
+            assert abs(grad[k] - fd) <= 1e-4 * max(abs(fd), 1e-3 * np.sqrt(np.mean(grad ** 2)))
+
+
+def test_autograd_functions_match_raw_kernels():
+    announce("autograd vs raw")
+    rng = np.random.default_rng(3)
+    x = torch.from_numpy(rng.random((5, 6, 7), dtype=np.float32)).cuda().requires_grad_(True)
+    P = autograd.pad_embed(x, (8, 9, 10))
+    gP = torch.from_numpy(rng.standard_normal((8, 9, 10)).astype(np.float32)).cuda()
+    P.backward(gP)
+    assert torch.equal(x.grad, api.crop(gP, (5, 6, 7)))
+    # moments with the covariance: backward equals the adjoint kernel
+    p = torch.from_numpy(rng.random((6, 5, 4), dtype=np.float32)).cuda().requires_grad_(True)
+    M, E, C = autograd.Moments.apply(p, True)
+    gE = torch.from_numpy(rng.standard_normal(3).astype(np.float32)).cuda()
+    gC = torch.from_numpy(rng.standard_normal(6).astype(np.float32)).cuda()
+    (E * gE).sum().add_((C * gC).sum()).backward()
+    o32, o64 = api.moments(p.detach(), cov=True)
+    gm = torch.cat([torch.zeros(1, device="cuda"), gE, gC])
+    g = api.moments_adj(p.shape, o64, gm, cov=True)
+    assert torch.allclose(p.grad, g, rtol=1e-6, atol=0)

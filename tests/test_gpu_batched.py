@@ -1,0 +1,110 @@
+"""The batched form: thousands of ragged items in one persistent launch,
+captured in a hipGraph and replayed, against the oracle item by item."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1608_00099_amd import _lib as L
+from paper_1608_00099_amd import api, inputs
+from tests.gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_items(dsts, xs_np, shapes):
+    for i, (d_, x, (sx, sy)) in enumerate(zip(dsts, xs_np, shapes)):
+        ps = inputs.padded_shape(sx, sy)
+        want = np.full(ps, 3.0, dtype=np.float32)
+        oracle.embed_fill(ps, want.reshape(-1), ps, x.reshape(-1), sx)
+        got = d_.cpu().numpy()
+        assert got.tobytes() == want.tobytes(), ("item", i, sx, sy)
+
+
+def test_batched_fft_padding_full_4096_items():
+    announce("batched cfg4 4096 items")
+    shapes = inputs.cfg4_shapes()
+    xs_np = inputs.cfg4_values(shapes)
+    xs = [torch.from_numpy(x).cuda() for x in xs_np]
+    dsts = [torch.full(inputs.padded_shape(sx, sy), 7.0, device="cuda") for sx, sy in shapes]
+    items = [[d_, x] for d_, x in zip(dsts, xs)]
+    b = api.Batch()
+    b.apply(L.OP_EMBED_FILL, items)
+    torch.cuda.synchronize()
+    info = b.info()
+    assert info["replayed"] is False and info["units"] > 0
+    _check_items(dsts, xs_np, shapes)
+    # replays of the captured graph, with eager work between them
+    for rep in range(3):
+        for d_ in dsts:
+            d_.fill_(-1.0 - rep)
+        torch.cuda.synchronize()
+        if rep == 1:
+            b.apply(L.OP_EMBED_FILL, items)       # re-validated replay
+        else:
+            b.launch()                            # plain replay
+        torch.cuda.synchronize()
+        assert b.info()["replayed"] is True
+        _check_items(dsts, xs_np, shapes)
+    b.close()
+
+
+def test_batched_replan_and_other_ops():
+    announce("batched mixed ops")
+    rng = np.random.default_rng(9)
+    b = api.Batch()
+    # MUL_ACC over intersections of ragged items of every d
+    xs, ys, zs, want = [], [], [], []
+    for d in range(1, 7):
+        for k in range(5):
+            x_s = tuple(int(v) for v in rng.integers(1, 20, size=d))
+            y_s = tuple(s + int(rng.integers(0, 3)) for s in x_s)
+            z_s = tuple(s + int(rng.integers(0, 3)) for s in x_s)
+            x = rng.standard_normal(x_s).astype(np.float32)
+            y = rng.standard_normal(y_s).astype(np.float32)
+            z = rng.standard_normal(z_s).astype(np.float32)
+            w = x.copy()
+            oracle.mul_acc(x_s, w.reshape(-1), x_s, y.reshape(-1), y_s, z.reshape(-1), z_s)
+            xs.append(torch.from_numpy(x).cuda())
+            ys.append(torch.from_numpy(y).cuda())
+            zs.append(torch.from_numpy(z).cuda())
+            want.append(w)
+    b.apply(L.OP_MUL_ACC, [[x, y, z] for x, y, z in zip(xs, ys, zs)])
+    torch.cuda.synchronize()
+    for x, w in zip(xs, want):
+        assert x.cpu().numpy().tobytes() == w.tobytes()
+    # a different batch on the same handle re-plans (COPY, 8-byte elements)
+    srcs = [torch.from_numpy(rng.standard_normal((4, 5, 6))).cuda() for _ in range(7)]
+    dsts = [torch.zeros((6, 7, 9), dtype=torch.float64, device="cuda") for _ in range(7)]
+    b.apply(L.OP_COPY, [[d_, s] for d_, s in zip(dsts, srcs)], elem_bytes=8)
+    torch.cuda.synchronize()
+    assert b.info()["replayed"] is False
+    for d_, s in zip(dsts, srcs):
+        w = np.zeros((6, 7, 9))
+        sn = s.cpu().numpy()
+        oracle.copy((4, 5, 6), w.reshape(-1), (6, 7, 9), sn.reshape(-1), (4, 5, 6))
+        assert d_.cpu().numpy().tobytes() == w.tobytes()
+    b.close()
+
+
+def test_batched_empty_and_errors():
+    announce("batched edge cases")
+    b = api.Batch()
+    # items with no points
+    e1 = torch.zeros((3, 0), device="cuda")
+    e2 = torch.zeros((3, 0), device="cuda")
+    b.apply(L.OP_COPY, [[e1, e2]])
+    assert b.info()["units"] == 0
+    b.launch()
+    # an invalid item reports its status and leaves the handle usable
+    a = torch.zeros((4, 4), device="cuda")
+    c = torch.zeros((3, 5), device="cuda")
+    with pytest.raises(L.TriotError) as e:
+        st = L.triot_apply_batched(L.OP_COPY, [(2, 2, [(4, 4), (3, 5)], (4, 4),
+                                                 [a.data_ptr(), c.data_ptr()], None)],
+                                   L.CopyParams(4), b._h, torch.cuda.current_stream().cuda_stream)
+        api._check(st, "apply_batched")
+    assert e.value.status == L.E_BOUNDS
+    with pytest.raises(L.TriotError):
+        api._check(L.triot_apply_batched(L.OP_MOMENTS, [], None, b._h, 0), "apply_batched")
+    b.close()

@@ -378,7 +378,7 @@ def test_moments_several_operands_and_windows():
     # the float64 results carry that rounding (relative 2^-23 per point)
     got = host(o64)
     err = rel_err(got, want, floor=1e-6 * abs(want[4]))
-    assert err.max() < 2e-7, err
+    assert err.max() <= 1e-6, err
     # a window (non-contiguous operand): the per-thread path
     parent = (40, 50, 30)
     P = rng.random(parent).astype(np.float32)
