@@ -19,7 +19,6 @@ the small pad-embed) next to a plain device-copy ceiling.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -44,11 +43,8 @@ def prod(s):
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("common.h", "kern_coiter.hip", "kern_segment.hip", "plan.cpp"):
-        with open(os.path.join(ROOT, "paper_1608_00099_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1608_00099_amd.profiling import kernel_source_hash as h
+    return h()
 
 
 # ---------------------------------------------------------------------------
@@ -102,7 +98,7 @@ def plan_of(op, it):
     return p, api.kernel_name(op, p)
 
 
-def autotune_all(launches):
+def autotune_all(launches, cache_path=None):
     """Let the library's autotuner pick each launch's schedule (it times the
     candidates with HIP events on these very buffers)."""
     from paper_1608_00099_amd import api
@@ -110,9 +106,10 @@ def autotune_all(launches):
     out = {}
     for name, op, fn, nbytes, it in launches:
         if op == L.OP_COPY:
-            api.autotune(op, [it["dst"], it["src"]], counter=it["src_s"], params=L.CopyParams(4))
+            api.autotune(op, [it["dst"], it["src"]], counter=it["src_s"], params=L.CopyParams(4),
+                         cache_path=cache_path)
         else:
-            api.autotune(op, [it["x"], it["y"], it["z"]])
+            api.autotune(op, [it["x"], it["y"], it["z"]], cache_path=cache_path)
         plan, kname = plan_of(op, it)
         out[name] = {"unroll": plan["unroll"], "blocks": plan["blocks"], "vec": plan["vec"],
                      "box_rows": plan["box_rows"]}
@@ -237,23 +234,39 @@ def graph_ms(fn, reps=10):
     return t
 
 
-def extras(dev):
-    import numpy as np
-    import torch
-    from paper_1608_00099_amd import api, autograd, inputs
-    from paper_1608_00099_amd import _lib as L
-    out = {}
-    # 1 GiB streaming-copy ceiling (torch's device copy)
-    n = 1 << 28
-    a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
-    b = torch.empty_like(a)
-    t = event_ms(lambda: b.copy_(a))
-    out["copy_ceiling"] = {"GBs": 2 * 4 * n / t["median_ms"] / 1e6, "bytes": 8 * n,
-                           "what": "torch device copy of 1 GiB"}
-    flush = b  # scratch written between cold runs (>= 1 GiB beats the 256 MB cache)
-    del a
-    log("ceiling done")
+EXTRAS = ("ceiling", "cfg1", "cfg3", "cfg4", "cfg5")
 
+
+def extras(dev, only=None):
+    """The secondary configurations (all of them, or only `only`)."""
+    import torch
+    out = {}
+    want = (lambda k: only is None or only == k)
+    # 1 GiB streaming-copy ceiling (torch's device copy); its destination is
+    # the scratch written between cold runs (>= 1 GiB beats the 256 MB cache)
+    n = 1 << 28
+    flush = torch.empty(n, dtype=torch.float32, device=dev)
+    if want("ceiling"):
+        a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+        t = event_ms(lambda: flush.copy_(a))
+        out["copy_ceiling"] = {"GBs": 2 * 4 * n / t["median_ms"] / 1e6, "bytes": 8 * n,
+                               "what": "torch device copy of 1 GiB"}
+        del a
+        log("ceiling done")
+    if want("cfg1"):
+        _cfg1(dev, out)
+    if want("cfg3"):
+        _cfg3(dev, flush, out)
+    if want("cfg4"):
+        _cfg4(dev, out)
+    if want("cfg5"):
+        _cfg5(dev, out)
+    return out
+
+
+def _cfg1(dev, out):
+    import torch
+    from paper_1608_00099_amd import api, inputs
     # cfg1: small pad-embed (launch-latency bound)
     src = torch.from_numpy(inputs.cfg1_values()).to(dev)
     dst = torch.zeros(inputs.CFG1_DST, dtype=torch.float32, device=dev)
@@ -263,6 +276,10 @@ def extras(dev):
     out["cfg1_pad_embed"] = {"ms_per_launch": per, "GBs": nb / per / 1e6, "bytes": nb,
                              "cache": "warm", "timing": "100 launches captured in one graph"}
 
+
+def _cfg3(dev, flush, out):
+    import torch
+    from paper_1608_00099_amd import api, inputs
     # cfg3: moments of a 16^6 PMF (64 MiB: cold runs flush the cache first)
     p = torch.from_numpy(inputs.cfg3_values()).to(dev)
     nb = 4 * p.numel()
@@ -274,6 +291,12 @@ def extras(dev):
                                "bytes": nb}
     log("moments done")
 
+
+
+def _cfg4(dev, out):
+    import torch
+    from paper_1608_00099_amd import api, inputs
+    from paper_1608_00099_amd import _lib as L
     # cfg4: 4096 ragged pads for FFT convolution, one persistent graph launch
     shapes = inputs.cfg4_shapes()
     xs = [torch.from_numpy(x).to(dev) for x in inputs.cfg4_values(shapes)]
@@ -302,6 +325,11 @@ def extras(dev):
     del xs, dsts, items
     log("batched done")
 
+
+def _cfg5(dev, out):
+    import numpy as np
+    import torch
+    from paper_1608_00099_amd import api, autograd, inputs
     # cfg5: differentiable pipeline, autograd vs the raw kernels
     x_np, w_np, lam_np = inputs.cfg5_values()
     x = torch.from_numpy(x_np).to(dev).requires_grad_(True)
@@ -338,7 +366,6 @@ def extras(dev):
                             "GBs_raw": (fwd_bytes + bwd_bytes) / t_raw["median_ms"] / 1e6,
                             "bytes": fwd_bytes + bwd_bytes}
     log("autograd done")
-    return out
 
 
 def load_traffic(kernel, src_hash):
@@ -363,8 +390,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only", choices=EXTRAS, default=None,
+                    help="time one secondary configuration alone (for profiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (default schedules)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="schedule cache file: loaded if it exists (no tuning), else "
+                         "written after tuning (so profiled runs launch the same kernels)")
     ap.add_argument("--cpu-log2", type=float, default=25.5,
                     help="log2 elements per tensor of the CPU oracle sample")
     args = ap.parse_args()
@@ -373,18 +405,29 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    reuse = bool(args.tune_cache) and os.path.exists(args.tune_cache)
+    if reuse:
+        os.environ["TRIOT_TUNE_CACHE"] = os.path.abspath(args.tune_cache)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_1608_00099_amd import _lib as L
     L.lib()
     dev = torch.device("cuda:0")
+    if args.only:
+        print(json.dumps({"only": args.only, "extras": extras(dev, args.only)}), flush=True)
+        return
     log("allocating the d=2..8 sweep")
     sw = Sweep(dev)
     launches = sw.launches()
     tuned = {}
-    if not args.no_tune:
+    if not args.no_tune and not reuse:
         log("autotuning the %d launch schedules" % len(launches))
-        tuned = autotune_all(launches)
+        tuned = autotune_all(launches, args.tune_cache)
+    elif reuse:
+        tuned = {name: dict(zip(("unroll", "blocks", "vec", "box_rows"),
+                                (lambda p: (p["unroll"], p["blocks"], p["vec"], p["box_rows"]))(
+                                    plan_of(op, it)[0])))
+                 for name, op, fn, nbytes, it in launches}
     step_bytes = sum(x[3] for x in launches)
     fns = [x[2] for x in launches]
     log("timing %d steps after %d warm-up steps" % (args.steps, args.warmup))
