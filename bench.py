@@ -111,51 +111,44 @@ def autotune_all(launches, cache_path=None):
         else:
             api.autotune(op, [it["x"], it["y"], it["z"]], cache_path=cache_path)
         plan, kname = plan_of(op, it)
-        out[name] = {"unroll": plan["unroll"], "blocks": plan["blocks"], "vec": plan["vec"],
+        out[name] = {"cache": plan["cache_policy"], "blocks": plan["blocks"], "vec": plan["vec"],
                      "box_rows": plan["box_rows"]}
     return out
 
 
 def time_steps(fns, steps, warmup):
+    """Time exactly `steps` steps of the launch sequence `fns`.  HIP events
+    recorded on the stream the kernels run on (the library enqueues on
+    torch's current stream) bracket every launch inside the timed region, so
+    each kernel's duration is the one it has in the real sequence (after a
+    different kernel over other buffers, not after itself).  Returns the
+    step time (ms, first to last event), the host wall time per step (ms)
+    and the per-launch durations [launch][step] (ms)."""
     import torch
     for _ in range(warmup):
         for f in fns:
             f()
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(fns) + 1)]
+          for _ in range(steps)]
+    # torch creates the HIP event at its first record: do that now, outside
+    # the timed region (a creation stall would starve the device there).
+    for row in ev:
+        for e in row:
+            e.record(s)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(s)
-    for _ in range(steps):
-        for f in fns:
+    for k in range(steps):
+        for i, f in enumerate(fns):
+            ev[k][i].record(s)
             f()
-    e1.record(s)
+        ev[k][len(fns)].record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
-
-
-def per_launch(launches, reps=5):
-    """Median duration (ms) of every launch, from HIP events recorded on the
-    stream the kernels run on (the library uses torch's current stream).
-    Each timed launch follows an untimed one, so the device is still busy
-    while the host enqueues the event pair and the kernel between them."""
-    import torch
-    s = torch.cuda.current_stream()
-    res = {}
-    for name, op, fn, nbytes, it in launches:
-        ms = []
-        for _ in range(reps):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            fn()
-            a.record(s)
-            fn()
-            b.record(s)
-            torch.cuda.synchronize()
-            ms.append(a.elapsed_time(b))
-        ms.sort()
-        res[name] = (ms[len(ms) // 2], ms[0], ms[-1])
-    return res
+    total = ev[0][0].elapsed_time(ev[-1][len(fns)])
+    per = [[ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(steps)] for i in range(len(fns))]
+    return total / steps, wall / steps * 1e3, per
 
 
 # ---------------------------------------------------------------------------
@@ -424,28 +417,29 @@ def main():
         log("autotuning the %d launch schedules" % len(launches))
         tuned = autotune_all(launches, args.tune_cache)
     elif reuse:
-        tuned = {name: dict(zip(("unroll", "blocks", "vec", "box_rows"),
-                                (lambda p: (p["unroll"], p["blocks"], p["vec"], p["box_rows"]))(
-                                    plan_of(op, it)[0])))
+        tuned = {name: dict(zip(("cache", "blocks", "vec", "box_rows"),
+                                (lambda p: (p["cache_policy"], p["blocks"], p["vec"],
+                                            p["box_rows"]))(plan_of(op, it)[0])))
                  for name, op, fn, nbytes, it in launches}
     step_bytes = sum(x[3] for x in launches)
     fns = [x[2] for x in launches]
     log("timing %d steps after %d warm-up steps" % (args.steps, args.warmup))
-    ms_step, wall_ms = time_steps(fns, args.steps, args.warmup)
+    ms_step, wall_ms, per = time_steps(fns, args.steps, args.warmup)
     value = step_bytes / (ms_step * 1e-3) / 1e9
     log("step %.3f ms, %.1f GB/s" % (ms_step, value))
 
-    # Per-launch durations and the dominant kernel's roofline.
-    pl = per_launch(launches)
+    # Per-launch durations (inside the timed steps) and the dominant
+    # kernel's roofline.
     per_op = {}
     by_kernel = {}
-    for name, op, fn, nbytes, it in launches:
+    for (name, op, fn, nbytes, it), ts in zip(launches, per):
         plan, kname = plan_of(op, it)
-        med = pl[name][0]
-        per_op[name] = {"ms": med, "GBs": nbytes / med / 1e6, "bytes": nbytes, "kernel": kname,
+        avg = sum(ts) / len(ts)
+        per_op[name] = {"ms": avg, "ms_min": min(ts), "ms_max": max(ts),
+                        "GBs": nbytes / avg / 1e6, "bytes": nbytes, "kernel": kname,
                         "box_rows": plan["box_rows"], "units": plan["units"]}
         k = by_kernel.setdefault(kname, {"ms": 0.0, "bytes": 0, "launches": 0})
-        k["ms"] += med
+        k["ms"] += avg
         k["bytes"] += nbytes
         k["launches"] += 1
     dom = max(by_kernel, key=lambda k: by_kernel[k]["ms"])

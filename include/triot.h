@@ -209,12 +209,15 @@ triot_status triot_batch_info(const triot_batch *handle, int64_t *n_units, int *
 
 /* ---- tuning ----------------------------------------------------------- */
 
-/* Time the candidate launch schedules (tile unroll, blocks per CU, box
- * rows, vector width) of this exact problem with HIP events on `stream`,
+/* Time the candidate launch schedules (vector width, cache policy, blocks
+ * per CU, unit order, box rows, work-unit size) of this exact problem with HIP events on `stream`,
  * keep the fastest for every later call with the same plan signature, and
  * append it to the JSON cache at cache_path (NULL = in memory only).  The
  * operation RUNS several times on the given buffers: pass scratch copies
- * for in-place ops.  The cache named by the environment variable
+ * for in-place ops.  Each candidate is timed cold, after a write over a
+ * 512 MiB device buffer that the call allocates and frees (larger than the
+ * memory-side cache); when it cannot be allocated, candidates are timed
+ * without it.  The cache named by the environment variable
  * TRIOT_TUNE_CACHE, if set, is loaded on first use; unreadable or corrupt
  * entries are ignored.  Synchronises `stream`. */
 triot_status triot_autotune(triot_op op, int n_tensors, int d, const int64_t *shapes,
@@ -225,6 +228,30 @@ triot_status triot_autotune(triot_op op, int n_tensors, int d, const int64_t *sh
 
 /* Forget every tuned schedule held in memory (the defaults apply again). */
 void triot_tune_reset(void);
+
+/* A launch schedule of the element-wise co-iteration kernels. */
+typedef struct triot_schedule {
+    int vec_max;             /* widest lane access in 4-byte words: 1, 2 or 4 */
+    int cache_policy;        /* 0 normal, 1 non-temporal loads and stores,
+                                2 non-temporal loads only */
+    int blocks_per_cu;       /* persistent workgroups per compute unit, 1..32 */
+    int box_rows_max;        /* rows per box (LDS row table), 1..1024 */
+    int unit_elems;          /* elements per work unit, 64..2^24 */
+    int unit_order;          /* 0: each workgroup takes a contiguous range of
+                                work units; 1: units dealt round-robin */
+} triot_schedule;
+
+/* Pin the schedule of one problem (same plan signature as triot_autotune):
+ * every later call with that signature uses it, until triot_tune_reset or
+ * another pin or tuning of the same signature.  No device work.  Returns
+ * TRIOT_E_INVALID for a knob out of range and TRIOT_E_UNSUPPORTED for the
+ * tuple-reading row kernels (moments and their adjoint), which have one
+ * schedule.  Any value in range gives the same results as the defaults
+ * (schedules change the speed only). */
+triot_status triot_schedule_set(triot_op op, int n_tensors, int d, const int64_t *shapes,
+                                const int64_t *counter_shape, void *const *tensors,
+                                const int64_t *bases, const void *params,
+                                const triot_schedule *schedule);
 
 /* ---- diagnostics -------------------------------------------------------- */
 
@@ -252,6 +279,9 @@ typedef struct triot_plan_info {
     int threads;             /* threads per workgroup */
     int unroll;              /* elements per thread per step */
     int inner_unit;          /* 1 when every operand is contiguous on the inner axis */
+    int cache_policy;        /* 0 normal, 1 non-temporal loads and stores,
+                                2 non-temporal loads only */
+    int unit_order;          /* 0 contiguous ranges, 1 round-robin */
 } triot_plan_info;
 
 triot_status triot_plan_describe(triot_op op, int n_tensors, int d, const int64_t *shapes,

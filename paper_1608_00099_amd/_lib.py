@@ -53,7 +53,14 @@ class PlanInfo(ctypes.Structure):
                 ("high_axes", ctypes.c_int), ("low_axes", ctypes.c_int),
                 ("box_rows", ctypes.c_int64), ("units", ctypes.c_int64),
                 ("blocks", ctypes.c_int), ("threads", ctypes.c_int), ("unroll", ctypes.c_int),
-                ("inner_unit", ctypes.c_int)]
+                ("inner_unit", ctypes.c_int), ("cache_policy", ctypes.c_int),
+                ("unit_order", ctypes.c_int)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("vec_max", ctypes.c_int), ("cache_policy", ctypes.c_int),
+                ("blocks_per_cu", ctypes.c_int), ("box_rows_max", ctypes.c_int),
+                ("unit_elems", ctypes.c_int), ("unit_order", ctypes.c_int)]
 
 
 class TriotError(RuntimeError):
@@ -66,7 +73,7 @@ class TriotError(RuntimeError):
 _lib = None
 
 EXPORTS = ["triot_apply", "triot_workspace_size", "triot_batch_create", "triot_batch_destroy",
-           "triot_apply_batched", "triot_batch_launch", "triot_batch_info", "triot_autotune", "triot_tune_reset",
+           "triot_apply_batched", "triot_batch_launch", "triot_batch_info", "triot_autotune", "triot_tune_reset", "triot_schedule_set",
            "triot_status_string", "triot_divmod_magic", "triot_plan_describe"]
 
 
@@ -100,6 +107,8 @@ def lib():
     L.triot_autotune.argtypes = [I, I, I, pI64, pI64, pP, pI64, P, P, P, SZ, P, ctypes.c_char_p]
     L.triot_tune_reset.restype = None
     L.triot_tune_reset.argtypes = []
+    L.triot_schedule_set.restype = I
+    L.triot_schedule_set.argtypes = [I, I, I, pI64, pI64, pP, pI64, P, ctypes.POINTER(Schedule)]
     L.triot_status_string.restype = ctypes.c_char_p
     L.triot_status_string.argtypes = [I]
     L.triot_divmod_magic.restype = I
@@ -184,6 +193,16 @@ def triot_autotune(op, n_tensors, d, shapes, counter_shape, tensors, bases, para
 
 def triot_tune_reset() -> None:
     lib().triot_tune_reset()
+
+
+def triot_schedule_set(op, n_tensors, d, shapes, counter_shape, tensors, bases, params,
+                       schedule) -> int:
+    shapes_a = _i64_array([v for s in shapes for v in s] if d else [])
+    counter_a = _i64_array(counter_shape) if counter_shape is not None else None
+    bases_a = _i64_array(bases) if bases is not None else None
+    return lib().triot_schedule_set(int(op), int(n_tensors), int(d), shapes_a, counter_a,
+                                    _ptr_array(tensors), bases_a, _params_ptr(params),
+                                    ctypes.byref(schedule))
 
 
 def triot_batch_create():

@@ -281,6 +281,23 @@ def autotune(op, tensors, shapes=None, counter=None, bases=None, params=None, ca
     _check(st, "autotune")
 
 
+def schedule_set(op, tensors, shapes=None, counter=None, bases=None, params=None, vec_max=4,
+                 cache_policy=1, blocks_per_cu=4, box_rows_max=1024, unit_elems=8192,
+                 unit_order=0):
+    """Pin the launch schedule of this exact problem (every later call with
+    the same plan signature uses it until tune_reset)."""
+    dev, shapes = _prep(tensors, shapes)
+    sch = L.Schedule(vec_max, cache_policy, blocks_per_cu, box_rows_max, unit_elems, unit_order)
+    st = L.triot_schedule_set(op, len(tensors), len(shapes[0]), shapes, counter,
+                              [_ptr(t) for t in tensors], bases, params, sch)
+    _check(st, "schedule_set")
+
+
+def tune_reset():
+    """Forget every tuned or pinned schedule (the defaults apply again)."""
+    L.triot_tune_reset()
+
+
 def describe(op, shapes, counter=None, ptrs=None, bases=None, params=None):
     """The launch plan triot_apply would use (no device work)."""
     shapes = [tuple(int(v) for v in s) for s in shapes]
@@ -293,7 +310,8 @@ def describe(op, shapes, counter=None, ptrs=None, bases=None, params=None):
             "extents": [info.extents[i] for i in range(info.dims)], "vec": info.vec,
             "high_axes": info.high_axes, "low_axes": info.low_axes, "box_rows": info.box_rows,
             "units": info.units, "blocks": info.blocks, "threads": info.threads,
-            "unroll": info.unroll, "inner_unit": info.inner_unit}
+            "unroll": info.unroll, "inner_unit": info.inner_unit,
+            "cache_policy": info.cache_policy, "unit_order": info.unit_order}
 
 
 _CO_OP = {0: 0, 1: 1, 2: 2, 3: 3, 6: 4, 7: 5}   # public op -> kernel template op
@@ -309,6 +327,6 @@ def kernel_name(op, plan):
         return "void triot::%s<%d, %s>(triot::SegPlan)" % (base, dmax, cov)
     rows1 = "true" if plan["box_rows"] == 1 else "false"
     unit = "true" if plan["inner_unit"] else "false"
-    u = 4 if op == L.OP_INDEX else plan["unroll"]
-    return "void triot::coiter_kernel<%d, %d, %d, %s, %s>(triot::CoPlan)" % (
-        _CO_OP[op], plan["vec"], u, rows1, unit)
+    cp = 0 if op == L.OP_INDEX else plan["cache_policy"]
+    return "void triot::coiter_kernel<%d, %d, %d, %s, %s, %d>(triot::CoPlan)" % (
+        _CO_OP[op], plan["vec"], plan["unroll"], rows1, unit, cp)

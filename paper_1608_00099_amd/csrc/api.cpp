@@ -39,6 +39,13 @@ std::mutex g_mu;
 std::unordered_map<std::string, Sched> g_sched;
 bool g_loaded = false;
 
+bool sched_valid(const Sched &s)
+{
+    return (s.vec_max == 1 || s.vec_max == 2 || s.vec_max == 4) && s.cache >= 0 && s.cache <= 2 &&
+           s.blocks_per_cu >= 1 && s.blocks_per_cu <= 32 && s.rb_max >= 1 && s.rb_max <= RB_MAX &&
+           s.pe_target >= 64 && s.pe_target <= (1 << 24) && (s.order == 0 || s.order == 1);
+}
+
 void load_cache_file(const char *path)
 {
     FILE *f = std::fopen(path, "r");
@@ -46,19 +53,17 @@ void load_cache_file(const char *path)
         return;
     char line[8192];
     while (std::fgets(line, sizeof line, f)) {
-        // {"key": "<key>", "vec": V, "unroll": U, "bpc": B, "rb": R, "pe": P}
+        // {"key": "<key>", "vec": V, "cache": C, "bpc": B, "order": O, "rb": R, "pe": P}
         char key[4096];
         Sched s;
         int n = std::sscanf(line,
-                            " {\"key\": \"%4095[^\"]\", \"vec\": %d, \"unroll\": %d, \"bpc\": %d, "
-                            "\"rb\": %d, \"pe\": %d}",
-                            key, &s.vec_max, &s.unroll, &s.blocks_per_cu, &s.rb_max, &s.pe_target);
-        if (n != 6)
+                            " {\"key\": \"%4095[^\"]\", \"vec\": %d, \"cache\": %d, \"bpc\": %d, "
+                            "\"order\": %d, \"rb\": %d, \"pe\": %d}",
+                            key, &s.vec_max, &s.cache, &s.blocks_per_cu, &s.order, &s.rb_max,
+                            &s.pe_target);
+        if (n != 7)
             continue;  // corrupt or foreign line: ignored
-        if ((s.vec_max != 1 && s.vec_max != 2 && s.vec_max != 4) ||
-            (s.unroll != 2 && s.unroll != 4 && s.unroll != 8) || s.blocks_per_cu < 1 ||
-            s.blocks_per_cu > 32 || s.rb_max < 1 || s.rb_max > RB_MAX || s.pe_target < 64 ||
-            s.pe_target > (1 << 24))
+        if (!sched_valid(s))
             continue;
         g_sched[key] = s;
     }
@@ -241,6 +246,8 @@ extern "C" triot_status triot_plan_describe(triot_op op, int n_tensors, int d, c
     info->threads = NT;
     info->unroll = L.unroll;
     info->inner_unit = L.unit ? 1 : 0;
+    info->cache_policy = L.cache;
+    info->unit_order = (int)P.interleave;
     return TRIOT_OK;
 }
 
@@ -272,24 +279,39 @@ extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const 
         (void)hipEventDestroy(ev0);
         return TRIOT_E_DEVICE;
     }
+    // Every candidate is timed cold: a write over a buffer larger than the
+    // memory-side cache (256 MB on MI355X) precedes each timed run, as the
+    // previous operation of a streaming sequence would.  Timing a launch
+    // right after itself would instead reward schedules that reuse what the
+    // last run left in that cache.
+    const size_t flush_bytes = size_t(512) << 20;
+    void *flush = nullptr;
+    if (hipMalloc(&flush, flush_bytes) != hipSuccess) {
+        flush = nullptr;               // no room: candidates are timed warm
+        (void)hipGetLastError();
+    }
+    int flush_val = 0;
     auto time_it = [&](const Sched &s, float *ms) -> triot_status {
         triot_status t = run_request(r, s, out, workspace, workspace_bytes, stream);  // warm-up
         if (t != TRIOT_OK)
             return t;
         const int reps = 5;
-        if (hipEventRecord(ev0, stream) != hipSuccess)
-            return TRIOT_E_DEVICE;
+        float v[reps];
         for (int i = 0; i < reps; ++i) {
+            if ((flush && hipMemsetAsync(flush, ++flush_val & 0xFF, flush_bytes, stream) !=
+                              hipSuccess) ||
+                hipEventRecord(ev0, stream) != hipSuccess)
+                return TRIOT_E_DEVICE;
             t = run_request(r, s, out, workspace, workspace_bytes, stream);
             if (t != TRIOT_OK)
                 return t;
+            if (hipEventRecord(ev1, stream) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess)
+                return TRIOT_E_DEVICE;
+            if (hipEventElapsedTime(&v[i], ev0, ev1) != hipSuccess)
+                return TRIOT_E_DEVICE;
         }
-        if (hipEventRecord(ev1, stream) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess)
-            return TRIOT_E_DEVICE;
-        float e = 0.f;
-        if (hipEventElapsedTime(&e, ev0, ev1) != hipSuccess)
-            return TRIOT_E_DEVICE;
-        *ms = e / reps;
+        std::sort(v, v + reps);
+        *ms = v[reps / 2];
         return TRIOT_OK;
     };
     Sched best;
@@ -297,8 +319,9 @@ extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const 
     st = time_it(best, &best_ms);
     // Coordinate descent over the knobs, each from the best so far.
     const int vecs[] = {4, 2, 1};
-    const int unrolls[] = {2, 4, 8};
-    const int bpcs[] = {2, 4, 8, 16};
+    const int caches[] = {1, 0, 2};
+    const int bpcs[] = {1, 2, 4, 8, 16};
+    const int orders[] = {0, 1};
     const int rbs[] = {32, 64, 128, 256};
     const int pes[] = {2048, 4096, 8192, 16384, 32768};
     for (int pass = 0; pass < 2 && st == TRIOT_OK; ++pass) {
@@ -323,16 +346,16 @@ extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const 
             }
         };
         sweep(&Sched::vec_max, vecs, 3);
-        // The unroll depth stays at its default: it names a different kernel
-        // instance, and measured differences between 2, 4 and 8 were within
-        // run-to-run noise; the grid, box and unit sizes carry the gains.
-        (void)unrolls;
-        sweep(&Sched::blocks_per_cu, bpcs, 4);
+        sweep(&Sched::cache, caches, 3);
+        sweep(&Sched::blocks_per_cu, bpcs, 5);
+        sweep(&Sched::order, orders, 2);
         sweep(&Sched::rb_max, rbs, 4);
         sweep(&Sched::pe_target, pes, 5);
     }
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
+    if (flush)
+        (void)hipFree(flush);
     if (st != TRIOT_OK)
         return st;
     const std::string key = sched_key(r);
@@ -345,13 +368,42 @@ extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const 
         FILE *f = std::fopen(cache_path, "a");
         if (f) {
             std::fprintf(f,
-                         "{\"key\": \"%s\", \"vec\": %d, \"unroll\": %d, \"bpc\": %d, \"rb\": %d, "
-                         "\"pe\": %d}\n",
-                         key.c_str(), best.vec_max, best.unroll, best.blocks_per_cu, best.rb_max,
+                         "{\"key\": \"%s\", \"vec\": %d, \"cache\": %d, \"bpc\": %d, "
+                         "\"order\": %d, \"rb\": %d, \"pe\": %d}\n",
+                         key.c_str(), best.vec_max, best.cache, best.blocks_per_cu, best.order,
+                         best.rb_max,
                          best.pe_target);
             std::fclose(f);
         }
     }
+    return TRIOT_OK;
+}
+
+extern "C" triot_status triot_schedule_set(triot_op op, int n_tensors, int d,
+                                           const int64_t *shapes, const int64_t *counter_shape,
+                                           void *const *tensors, const int64_t *bases,
+                                           const void *params, const triot_schedule *schedule)
+{
+    if (!schedule)
+        return TRIOT_E_INVALID;
+    Request r;
+    triot_status st = validate(op, n_tensors, d, shapes, counter_shape, tensors, bases, params, &r);
+    if (st != TRIOT_OK)
+        return st;
+    if (is_segment_op(op))
+        return TRIOT_E_UNSUPPORTED;
+    Sched s;
+    s.vec_max = schedule->vec_max;
+    s.cache = schedule->cache_policy;
+    s.blocks_per_cu = schedule->blocks_per_cu;
+    s.rb_max = schedule->box_rows_max;
+    s.pe_target = schedule->unit_elems;
+    s.order = schedule->unit_order;
+    if (!sched_valid(s))
+        return TRIOT_E_INVALID;
+    std::lock_guard<std::mutex> g(g_mu);
+    ensure_loaded();
+    g_sched[sched_key(r)] = s;
     return TRIOT_OK;
 }
 

@@ -42,7 +42,8 @@ struct AxisDiv {
 //
 // The planned counter has D axes (extent-1 axes dropped, adjacent axes
 // merged where every operand is contiguous across them): D-1 outer axes
-// and one inner axis of extent L, all in units of `vec` 4-byte words.
+// and one inner axis of extent L in units of `vec` 4-byte words (outer
+// strides and bases in words).
 // The outer axes split into `nhigh` high axes and `nlow` low axes.  A
 // *box* is one value of the high axes: RB = prod(low extents) rows of L
 // elements.  Every workgroup tabulates, once, the offset of each box row
@@ -63,6 +64,8 @@ struct CoPlan {
     uint32_t esz;        // bytes per vector element (4 * vec)
     uint32_t vec;
     uint32_t unit;       // 1 when every inner stride is 1
+    uint32_t interleave; // unit order: 0 a contiguous range of units per
+                         // workgroup, 1 units dealt round-robin
     // Split axis: the outermost low axis may be the lower part (m digits)
     // of a counter axis of extent `sc` whose upper part (ceil(sc/m) blocks)
     // is the innermost high axis.  The last block covers sc - hi*m < m
@@ -74,11 +77,11 @@ struct CoPlan {
     uint32_t rows_below; // box rows per low digit of the split axis
     uint32_t sbound[MAXT];            // window extent on the split axis (NOBOUND = none)
     AxisDiv ax[MAXD];                 // outer axes, outermost first
-    int64_t stride[MAXT][MAXD];       // outer strides per operand (vector units)
+    int64_t stride[MAXT][MAXD];       // outer strides per operand (4-byte words)
     uint32_t bound[MAXT][MAXD];       // window extent per outer axis (NOBOUND = unchecked)
     uint32_t ibound[MAXT];            // window extent on the inner axis
     uint32_t istride[MAXT];           // inner stride (vector units)
-    int64_t base[MAXT];               // vector units
+    int64_t base[MAXT];               // 4-byte words
     uint64_t ptr[MAXT];               // device byte addresses
     uint64_t npoints;                 // counter points (INDEX output leading dimension)
     uint64_t cstride[MAXD];           // counter flat stride of each high axis (INDEX)

@@ -43,14 +43,28 @@ __device__ __forceinline__ uint32_t logical_block()
 #define GLOBAL __attribute__((address_space(1)))
 typedef GLOBAL char gchar;
 
-template <class T> __device__ __forceinline__ T gload(const gchar *p, uint32_t off)
+// Cache policy of a launch (a schedule knob): CP_NONTEMP_LS marks loads and
+// stores non-temporal (streamed past the caches, the right hint for data
+// touched once), CP_NONTEMP_L the loads only (windowed stores that leave
+// partial cache lines can merge better in L2 when cached normally).
+enum { CP_NORMAL = 0, CP_NONTEMP_LS = 1, CP_NONTEMP_L = 2 };
+
+template <class T, int CP> __device__ __forceinline__ T gload(const gchar *p, uint32_t off)
 {
-    return *(const GLOBAL T *)(p + off);
+    const GLOBAL T *a = (const GLOBAL T *)(p + off);
+    if constexpr (CP == CP_NORMAL)
+        return *a;
+    else
+        return __builtin_nontemporal_load(a);
 }
 
-template <class T> __device__ __forceinline__ void gstore(gchar *p, uint32_t off, T v)
+template <class T, int CP> __device__ __forceinline__ void gstore(gchar *p, uint32_t off, T v)
 {
-    *(GLOBAL T *)(p + off) = v;
+    GLOBAL T *a = (GLOBAL T *)(p + off);
+    if constexpr (CP == CP_NONTEMP_LS)
+        __builtin_nontemporal_store(v, a);
+    else
+        *a = v;
 }
 
 template <int V> struct Vec;
@@ -58,13 +72,14 @@ template <> struct Vec<1> {
     typedef uint32_t U;
     typedef float F;
 };
+// Vectors are only 4-byte aligned in memory (rows may start at any word).
 template <> struct Vec<2> {
-    typedef uint32_t U __attribute__((ext_vector_type(2)));
-    typedef float F __attribute__((ext_vector_type(2)));
+    typedef uint32_t U __attribute__((ext_vector_type(2), aligned(4)));
+    typedef float F __attribute__((ext_vector_type(2), aligned(4)));
 };
 template <> struct Vec<4> {
-    typedef uint32_t U __attribute__((ext_vector_type(4)));
-    typedef float F __attribute__((ext_vector_type(4)));
+    typedef uint32_t U __attribute__((ext_vector_type(4), aligned(4)));
+    typedef float F __attribute__((ext_vector_type(4), aligned(4)));
 };
 
 struct RowTable {
@@ -74,8 +89,10 @@ struct RowTable {
 };
 
 // Tabulate the box rows: decode each row over the low axes and store, per
-// operand, (row offset - row * L * istride) * esz so that an element e of
-// the box sits at table[row] + e * istride * esz bytes from the box base.
+// operand, row offset * 4 - row * L * istride * esz (bytes; row offsets are
+// in 4-byte words, the inner axis in vectors of esz bytes) so that element
+// e of the box sits at table[row] + e * istride * esz bytes from the box
+// base.
 __device__ void fill_table(const CoPlan &P, RowTable &T)
 {
     const uint32_t n = P.n, nhigh = P.nhigh, nlow = P.nlow;
@@ -108,7 +125,7 @@ __device__ void fill_table(const CoPlan &P, RowTable &T)
 #pragma unroll
         for (int k = 0; k < MAXT; ++k)
             if (k < (int)n)
-                T.off[k][r] = (rel[k] - r * P.L * P.istride[k]) * P.esz;
+                T.off[k][r] = rel[k] * 4u - r * P.L * P.istride[k] * P.esz;
         // t now holds the outermost low digit (the split axis' digit if split)
         T.mask[r] = mask | (t << 8);
     }
@@ -123,7 +140,7 @@ template <> struct OpInfo<CO_MUL_ADJ> { static constexpr int N = 5; static const
 template <> struct OpInfo<CO_INDEX> { static constexpr int N = MAXT; static constexpr bool PRED = false; };
 
 // Process one work unit (a part of one box).
-template <int OP, int V, int U, bool ROWS1, bool UNIT>
+template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP>
 __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const RowTable &T)
 {
     typedef typename Vec<V>::U VU;
@@ -198,14 +215,14 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
 #pragma unroll
         for (int k = 0; k < N; ++k)
             if (k < (int)n)
-                bb[k] += (int64_t)e0 * P.istride[k];
+                bb[k] += (int64_t)e0 * P.istride[k] * V;
     }
     constexpr uint32_t esz = 4u * V;   // == P.esz: the launcher picks V = P.vec
     gchar *bp[N];
     uint32_t isb[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        bp[k] = (gchar *)(uintptr_t)(P.ptr[k < (int)n ? k : 0]) + bb[k] * (int64_t)esz;
+        bp[k] = (gchar *)(uintptr_t)(P.ptr[k < (int)n ? k : 0]) + bb[k] * (int64_t)4;
         isb[k] = UNIT ? esz : P.istride[k < (int)n ? k : 0] * esz;
     }
 
@@ -257,50 +274,50 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u])
-                    v[u] = gload<VU>(bp[1], off[1][u]);
+                    v[u] = gload<VU, CP>(bp[1], off[1][u]);
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u])
-                    gstore<VU>(bp[0], off[0][u], v[u]);
+                    gstore<VU, CP>(bp[0], off[0][u], v[u]);
         } else if constexpr (OP == CO_FILL) {
             VU v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 v[u] = (VU)0u;
                 if (valid[u] && (pm[u] & 2u))
-                    v[u] = gload<VU>(bp[1], off[1][u]);
+                    v[u] = gload<VU, CP>(bp[1], off[1][u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u])
-                    gstore<VU>(bp[0], off[0][u], v[u]);
+                    gstore<VU, CP>(bp[0], off[0][u], v[u]);
         } else if constexpr (OP == CO_MUL_ACC) {
             VF x[U], y[U], z[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u]) {
-                    x[u] = gload<VF>(bp[0], off[0][u]);
-                    y[u] = gload<VF>(bp[1], off[1][u]);
-                    z[u] = gload<VF>(bp[2], off[2][u]);
+                    x[u] = gload<VF, CP>(bp[0], off[0][u]);
+                    y[u] = gload<VF, CP>(bp[1], off[1][u]);
+                    z[u] = gload<VF, CP>(bp[2], off[2][u]);
                 }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u]) {
                     VF prod = y[u] * z[u];       // rounded once (no contraction)
-                    gstore<VF>(bp[0], off[0][u], x[u] + prod);
+                    gstore<VF, CP>(bp[0], off[0][u], x[u] + prod);
                 }
         } else if constexpr (OP == CO_MUL) {
             VF a[U], b[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u]) {
-                    a[u] = gload<VF>(bp[1], off[1][u]);
-                    b[u] = gload<VF>(bp[2], off[2][u]);
+                    a[u] = gload<VF, CP>(bp[1], off[1][u]);
+                    b[u] = gload<VF, CP>(bp[2], off[2][u]);
                 }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u])
-                    gstore<VF>(bp[0], off[0][u], a[u] * b[u]);
+                    gstore<VF, CP>(bp[0], off[0][u], a[u] * b[u]);
         } else if constexpr (OP == CO_MUL_ADJ) {
             // operands: 0 ga, 1 gb, 2 gout, 3 a, 4 b
             VF g[U], a[U], b[U];
@@ -311,11 +328,11 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                 b[u] = (VF)0.0f;
                 const bool inI = valid[u] && (pm[u] & 4u);
                 if (inI) {
-                    g[u] = gload<VF>(bp[2], off[2][u]);
+                    g[u] = gload<VF, CP>(bp[2], off[2][u]);
                     if (pm[u] & 2u)
-                        a[u] = gload<VF>(bp[3], off[3][u]);
+                        a[u] = gload<VF, CP>(bp[3], off[3][u]);
                     if (pm[u] & 1u)
-                        b[u] = gload<VF>(bp[4], off[4][u]);
+                        b[u] = gload<VF, CP>(bp[4], off[4][u]);
                 }
             }
 #pragma unroll
@@ -324,9 +341,9 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                     continue;
                 const bool inI = (pm[u] & 4u) != 0;
                 if (pm[u] & 1u)
-                    gstore<VF>(bp[0], off[0][u], inI ? g[u] * b[u] : (VF)0.0f);
+                    gstore<VF, CP>(bp[0], off[0][u], inI ? g[u] * b[u] : (VF)0.0f);
                 if (pm[u] & 2u)
-                    gstore<VF>(bp[1], off[1][u], inI ? g[u] * a[u] : (VF)0.0f);
+                    gstore<VF, CP>(bp[1], off[1][u], inI ? g[u] * a[u] : (VF)0.0f);
             }
         } else if constexpr (OP == CO_INDEX) {
             // Element offsets (base included) of every operand, row-major
@@ -347,7 +364,7 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
     }
 }
 
-template <int OP, int V, int U, bool ROWS1, bool UNIT>
+template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP>
 __global__ __launch_bounds__(NT) void coiter_kernel(const CoPlan P)
 {
     __shared__ RowTable T;
@@ -357,10 +374,16 @@ __global__ __launch_bounds__(NT) void coiter_kernel(const CoPlan P)
     }
     const uint32_t lb = logical_block();
     const uint32_t g = gridDim.x;
-    const uint32_t u0 = (uint32_t)(((uint64_t)lb * P.nunits) / g);
-    const uint32_t u1 = (uint32_t)(((uint64_t)(lb + 1) * P.nunits) / g);
-    for (uint32_t u = u0; u < u1; ++u)
-        run_unit<OP, V, U, ROWS1, UNIT>(P, u, T);
+    if (P.interleave) {
+        // round-robin: at any moment the grid sweeps one window of memory
+        for (uint64_t u = lb; u < P.nunits; u += g)
+            run_unit<OP, V, U, ROWS1, UNIT, CP>(P, (uint32_t)u, T);
+    } else {
+        const uint32_t u0 = (uint32_t)(((uint64_t)lb * P.nunits) / g);
+        const uint32_t u1 = (uint32_t)(((uint64_t)(lb + 1) * P.nunits) / g);
+        for (uint32_t u = u0; u < u1; ++u)
+            run_unit<OP, V, U, ROWS1, UNIT, CP>(P, u, T);
+    }
 }
 
 // ---------------------------------------------------------------------
@@ -418,14 +441,14 @@ __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ 
         const uint32_t lu = u - first;
         if (rows1) {
             if (P.unit)
-                run_unit<OP, 1, U, true, true>(P, lu, T);
+                run_unit<OP, 1, U, true, true, CP_NORMAL>(P, lu, T);
             else
-                run_unit<OP, 1, U, true, false>(P, lu, T);
+                run_unit<OP, 1, U, true, false, CP_NORMAL>(P, lu, T);
         } else {
             if (P.unit)
-                run_unit<OP, 1, U, false, true>(P, lu, T);
+                run_unit<OP, 1, U, false, true, CP_NORMAL>(P, lu, T);
             else
-                run_unit<OP, 1, U, false, false>(P, lu, T);
+                run_unit<OP, 1, U, false, false, CP_NORMAL>(P, lu, T);
         }
     }
 }
@@ -434,55 +457,56 @@ __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ 
 // Host-side launchers
 // ---------------------------------------------------------------------
 
-template <int OP, int V, int U, bool ROWS1, bool UNIT>
+template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP>
 static hipError_t go(const CoLaunch &L, hipStream_t st)
 {
-    hipLaunchKernelGGL((coiter_kernel<OP, V, U, ROWS1, UNIT>), dim3(L.blocks), dim3(NT), 0, st,
-                       L.plan);
+    hipLaunchKernelGGL((coiter_kernel<OP, V, U, ROWS1, UNIT, CP>), dim3(L.blocks), dim3(NT), 0,
+                       st, L.plan);
     return hipGetLastError();
 }
 
-template <int OP, int V, int U>
+template <int OP, int V, int U, int CP>
 static hipError_t pick_rows(const CoLaunch &L, hipStream_t st)
 {
     if (L.rows1)
-        return L.unit ? go<OP, V, U, true, true>(L, st) : go<OP, V, U, true, false>(L, st);
-    return L.unit ? go<OP, V, U, false, true>(L, st) : go<OP, V, U, false, false>(L, st);
+        return L.unit ? go<OP, V, U, true, true, CP>(L, st) : go<OP, V, U, true, false, CP>(L, st);
+    return L.unit ? go<OP, V, U, false, true, CP>(L, st) : go<OP, V, U, false, false, CP>(L, st);
 }
 
-template <int OP, int U>
+template <int OP, int CP>
 static hipError_t pick_vec(const CoLaunch &L, hipStream_t st)
 {
+    constexpr int U = 4;
     if constexpr (OP == CO_INDEX) {
-        return pick_rows<OP, 1, U>(L, st);
+        return pick_rows<OP, 1, U, CP>(L, st);
     } else {
         switch (L.plan.vec) {
-        case 4: return pick_rows<OP, 4, U>(L, st);
-        case 2: return pick_rows<OP, 2, U>(L, st);
-        default: return pick_rows<OP, 1, U>(L, st);
+        case 4: return pick_rows<OP, 4, U, CP>(L, st);
+        case 2: return pick_rows<OP, 2, U, CP>(L, st);
+        default: return pick_rows<OP, 1, U, CP>(L, st);
         }
     }
 }
 
 template <int OP>
-static hipError_t pick_unroll(const CoLaunch &L, hipStream_t st)
+static hipError_t pick_cache(const CoLaunch &L, hipStream_t st)
 {
-    if (L.unroll >= 8)
-        return pick_vec<OP, 8>(L, st);
-    if (L.unroll <= 2)
-        return pick_vec<OP, 2>(L, st);
-    return pick_vec<OP, 4>(L, st);
+    switch (L.cache) {
+    case CP_NONTEMP_LS: return pick_vec<OP, CP_NONTEMP_LS>(L, st);
+    case CP_NONTEMP_L: return pick_vec<OP, CP_NONTEMP_L>(L, st);
+    default: return pick_vec<OP, CP_NORMAL>(L, st);
+    }
 }
 
 hipError_t launch_coiter(int co_op, const CoLaunch &L, hipStream_t st)
 {
     switch (co_op) {
-    case CO_COPY: return pick_unroll<CO_COPY>(L, st);
-    case CO_FILL: return pick_unroll<CO_FILL>(L, st);
-    case CO_MUL_ACC: return pick_unroll<CO_MUL_ACC>(L, st);
-    case CO_MUL: return pick_unroll<CO_MUL>(L, st);
-    case CO_MUL_ADJ: return pick_unroll<CO_MUL_ADJ>(L, st);
-    case CO_INDEX: return pick_vec<CO_INDEX, 4>(L, st);
+    case CO_COPY: return pick_cache<CO_COPY>(L, st);
+    case CO_FILL: return pick_cache<CO_FILL>(L, st);
+    case CO_MUL_ACC: return pick_cache<CO_MUL_ACC>(L, st);
+    case CO_MUL: return pick_cache<CO_MUL>(L, st);
+    case CO_MUL_ADJ: return pick_cache<CO_MUL_ADJ>(L, st);
+    case CO_INDEX: return pick_vec<CO_INDEX, CP_NORMAL>(L, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -421,23 +421,21 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
         m[nm++] = m[i];
     const int D = nm;
 
-    // 4. Vector width: every operand contiguous on the inner axis, the inner
-    //    extent, every outer stride, base, window bound and address a
-    //    multiple of the width.
+    // 4. Vector width: every operand contiguous on the inner axis, and the
+    //    inner extent and every inner window bound a multiple of the width,
+    //    so that a vector never straddles two rows.  Addresses need only be
+    //    4-byte aligned: multi-dword global accesses take any dword address
+    //    on CDNA.  Strides and bases stay in 4-byte words.
     const Ax &in = m[D - 1];
     int vec = 1;
     if (r.op != TRIOT_OP_INDEX) {
         for (int v = std::min(4, std::max(1, s.vec_max)); v > 1; v >>= 1) {
             bool ok = (in.c % v) == 0 && in.c / v >= 2;
             for (int k = 0; k < n && ok; ++k) {
-                if (in.S[k] != 1 || base[k] % v != 0 ||
-                    ((uintptr_t)r.ptr[k] % (4 * (uintptr_t)v)) != 0)
+                if (in.S[k] != 1 || ((uintptr_t)r.ptr[k] % 4) != 0)
                     ok = false;
                 if (in.B[k] != -1 && in.B[k] % v != 0)
                     ok = false;
-                for (int i = 0; i < D - 1 && ok; ++i)
-                    if (m[i].S[k] % v != 0)
-                        ok = false;
             }
             if (ok) {
                 vec = v;
@@ -479,12 +477,14 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
         if ((unsigned __int128)rows * L * L > ((unsigned __int128)1 << 32))
             return false;
         for (int k = 0; k < n; ++k) {
-            int64_t span = (L - 1) * is[k];
+            // byte span of one box in operand k (inner rows in vectors,
+            // outer strides in words)
+            __int128 span = (__int128)(L - 1) * is[k] * esz;
             for (int j = first; j < nouter; ++j)
-                span += (m[j].c - 1) * (m[j].S[k] / vec);
+                span += (__int128)(m[j].c - 1) * m[j].S[k] * 4;
             if (split_axis >= 0)
-                span += (mm - 1) * (m[split_axis].S[k] / vec);
-            if ((span + 1) * (int64_t)esz >= (int64_t(1) << 31))
+                span += (__int128)(mm - 1) * m[split_axis].S[k] * 4;
+            if (span + esz >= ((__int128)1 << 31))
                 return false;
         }
         return true;
@@ -595,6 +595,7 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     P.esz = esz;
     P.vec = (uint32_t)vec;
     P.unit = unit ? 1u : 0u;
+    P.interleave = s.order ? 1u : 0u;
     P.split = split ? 1u : 0u;
     P.sm = split ? (uint32_t)mm : 1u;
     P.sc = split ? (uint32_t)m[a].c : 1u;
@@ -613,7 +614,7 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
         else
             P.ax[i] = trivial_div();
         for (int k = 0; k < n; ++k) {
-            P.stride[k][i] = kx[i].S[k] / vec;
+            P.stride[k][i] = kx[i].S[k];
             if (kx[i].B[k] >= 0) {
                 P.bound[k][i] = (uint32_t)kx[i].B[k];
                 predmask |= 1u << k;
@@ -641,7 +642,7 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
         } else {
             P.ibound[k] = NOBOUND;
         }
-        P.base[k] = base[k] / vec;
+        P.base[k] = base[k];
         P.ptr[k] = (uint64_t)(uintptr_t)r.ptr[k];
     }
     P.predmask = predmask;
@@ -654,7 +655,8 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     if (blocks > 8)
         blocks = (blocks + 7) / 8 * 8;
     out->blocks = std::max(blocks, 1);
-    out->unroll = s.unroll;
+    out->unroll = 4;
+    out->cache = s.cache;
     out->rows1 = (RB == 1);
     out->unit = unit;
     return TRIOT_OK;

@@ -14,8 +14,10 @@ namespace triot {
 // Launch schedule knobs (defaults, or the autotuner's choice).
 struct Sched {
     int vec_max = 4;        // widest vector (words) allowed: 1, 2 or 4
-    int unroll = 4;         // elements per thread per step: 2, 4 or 8
+    int cache = 1;          // cache policy: 0 normal, 1 non-temporal loads and
+                            // stores, 2 non-temporal loads only
     int blocks_per_cu = 4;  // persistent workgroups per CU
+    int order = 0;          // unit order: 0 blocked ranges, 1 round-robin
     int rb_max = RB_MAX;    // rows per box (LDS table) upper bound
     int pe_target = 8192;   // elements per work unit
 };
@@ -39,7 +41,8 @@ struct CoLaunch {
     int dims;                 // the merged counter (before any split)
     int64_t extents[MAXD];    // its extents, inner axis in elements
     int blocks;
-    int unroll;
+    int unroll;               // elements per thread per step (fixed: 4)
+    int cache;                // cache policy (Sched::cache)
     bool rows1;     // RB == 1
     bool unit;      // every inner stride is 1
 };
