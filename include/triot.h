@@ -215,9 +215,9 @@ triot_status triot_batch_info(const triot_batch *handle, int64_t *n_units, int *
  * append it to the JSON cache at cache_path (NULL = in memory only).  The
  * operation RUNS several times on the given buffers: pass scratch copies
  * for in-place ops.  Each candidate is timed cold, after a write over a
- * 512 MiB device buffer that the call allocates and frees (larger than the
- * memory-side cache); when it cannot be allocated, candidates are timed
- * without it.  The cache named by the environment variable
+ * 512 MiB device buffer (larger than the memory-side cache) that the first
+ * tuning on a device allocates and triot_tune_reset frees; when it cannot be
+ * allocated, candidates are timed without it.  The cache named by the environment variable
  * TRIOT_TUNE_CACHE, if set, is loaded on first use; unreadable or corrupt
  * entries are ignored.  Synchronises `stream`. */
 triot_status triot_autotune(triot_op op, int n_tensors, int d, const int64_t *shapes,
@@ -226,7 +226,9 @@ triot_status triot_autotune(triot_op op, int n_tensors, int d, const int64_t *sh
                             void *workspace, size_t workspace_bytes, hipStream_t stream,
                             const char *cache_path);
 
-/* Forget every tuned schedule held in memory (the defaults apply again). */
+/* Forget every tuned or pinned schedule held in memory (the defaults apply
+ * again) and free the autotuner's flush buffers.  Not to be called while a
+ * triot_autotune call is running. */
 void triot_tune_reset(void);
 
 /* A launch schedule of the element-wise co-iteration kernels. */

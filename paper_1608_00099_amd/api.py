@@ -323,8 +323,11 @@ def kernel_name(op, plan):
     if plan["kernel"] == 1:
         cov = "true" if plan.get("cov") else "false"
         dmax = 8 if plan["dims"] <= 8 else 32
-        base = "moments_kernel" if op == L.OP_MOMENTS else "moments_adj_kernel"
-        return "void triot::%s<%d, %s>(triot::SegPlan)" % (base, dmax, cov)
+        if op == L.OP_MOMENTS:
+            dm = plan["dims"] if plan.get("cov") else dmax
+            vec = "true" if plan["vec"] == 4 else "false"
+            return "void triot::moments_kernel<%d, %s, %s>(triot::SegPlan)" % (dm, cov, vec)
+        return "void triot::moments_adj_kernel<%d, %s>(triot::SegPlan)" % (dmax, cov)
     rows1 = "true" if plan["box_rows"] == 1 else "false"
     unit = "true" if plan["inner_unit"] else "false"
     cp = 0 if op == L.OP_INDEX else plan["cache_policy"]

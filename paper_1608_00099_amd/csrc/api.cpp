@@ -80,6 +80,30 @@ void ensure_loaded()
         load_cache_file(p);
 }
 
+// The autotuner's cold-cache flush buffer, one per device, kept from the
+// first tuning until triot_tune_reset (allocating and freeing it per call
+// would leave deferred unmaps that stall later work on the device).
+constexpr size_t kFlushBytes = size_t(512) << 20;
+std::unordered_map<int, void *> g_flush;
+
+void *flush_buffer()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return nullptr;
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_flush.find(dev);
+    if (it != g_flush.end())
+        return it->second;
+    void *p = nullptr;
+    if (hipMalloc(&p, kFlushBytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    g_flush[dev] = p;
+    return p;
+}
+
 Sched sched_for(const Request &r)
 {
     std::lock_guard<std::mutex> g(g_mu);
@@ -221,7 +245,7 @@ extern "C" triot_status triot_plan_describe(triot_op op, int n_tensors, int d, c
         for (int i = 0; i < (int)L.plan.D - 1; ++i)
             info->extents[i] = L.plan.ax[i].c;
         info->extents[L.plan.D - 1] = L.plan.L;
-        info->vec = 1;
+        info->vec = L.plan.vec4 ? 4 : 1;
         info->units = (int64_t)L.plan.ntiles;
         info->blocks = L.blocks;
         info->threads = NT;
@@ -258,6 +282,10 @@ extern "C" void triot_tune_reset(void)
     std::lock_guard<std::mutex> g(g_mu);
     g_sched.clear();
     g_loaded = true;  // an explicit reset also forgets the environment's cache
+    for (auto &kv : g_flush)
+        if (kv.second)
+            (void)hipFree(kv.second);
+    g_flush.clear();
 }
 
 extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const int64_t *shapes,
@@ -284,12 +312,8 @@ extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const 
     // previous operation of a streaming sequence would.  Timing a launch
     // right after itself would instead reward schedules that reuse what the
     // last run left in that cache.
-    const size_t flush_bytes = size_t(512) << 20;
-    void *flush = nullptr;
-    if (hipMalloc(&flush, flush_bytes) != hipSuccess) {
-        flush = nullptr;               // no room: candidates are timed warm
-        (void)hipGetLastError();
-    }
+    const size_t flush_bytes = kFlushBytes;
+    void *flush = flush_buffer();      // null when there is no room: timed warm
     int flush_val = 0;
     auto time_it = [&](const Sched &s, float *ms) -> triot_status {
         triot_status t = run_request(r, s, out, workspace, workspace_bytes, stream);  // warm-up
@@ -354,8 +378,6 @@ extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const 
     }
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
-    if (flush)
-        (void)hipFree(flush);
     if (st != TRIOT_OK)
         return st;
     const std::string key = sched_key(r);

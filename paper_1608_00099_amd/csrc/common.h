@@ -93,15 +93,16 @@ struct CoPlan {
 // Logical axes only (extent-1 axes dropped, no merging, the tuple is read):
 // D axes, D-1 outer and the inner one of extent L.  Each row splits into G
 // segments of at most S elements; a thread folds one segment at a time.
-// When every operand is contiguous over the counter (`full`), a workgroup
-// stages its NT consecutive segments through LDS with coalesced accesses.
+// The moments pass loads a segment with 16-byte accesses when `vec4`; the
+// adjoint stages NT consecutive segments through LDS when `full`.
 struct SegPlan {
     uint32_t D, n;
     uint32_t d_orig;
     uint32_t L, S, G;
     AxisDiv gdiv;             // segment -> (row, part of row); c == 1 means G == 1
     uint32_t rows;            // counter rows (< 2^32)
-    uint32_t full;
+    uint32_t full;            // every operand contiguous over the counter
+    uint32_t vec4;            // every operand contiguous along the row and L % 4 == 0
     uint32_t flags;           // TRIOT_MOMENTS_* bits
     uint32_t nblocks;         // grid size (moments: number of partials)
     uint32_t nterms;          // accumulated terms: 1 + D (+ D(D+1)/2)

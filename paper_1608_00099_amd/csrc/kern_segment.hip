@@ -4,23 +4,22 @@
 //
 // One thread per row segment (at most SEG_MAX consecutive elements of one
 // counter row).  Inside a segment only the inner coordinate j varies, so the
-// per-element work is three float64 sums,
-//     r0 = sum w,  r1 = sum w*jl,  r2 = sum w*jl^2      (jl = j - j0),
-// and the outer coordinates enter once per segment ("row factoring").  The
-// coordinates are shifted by the centre (c_i - 1)/2 of every axis, which keeps
-// the covariance free of cancellation (the shifted-data variance algorithm of
-// Chan, Golub & LeVeque).  When the operands are contiguous over the counter,
-// a workgroup stages its NT consecutive segments through LDS, so global
-// memory sees only coalesced, lane-consecutive accesses.
+// per-element work is three float64 sums, taken as running sums that never
+// form j (three additions per element), and the outer coordinates enter
+// once per segment ("row factoring").  The coordinates are shifted by the
+// centre (c_i - 1)/2 of every axis, which keeps the covariance free of
+// cancellation (the shifted-data variance algorithm of Chan, Golub &
+// LeVeque).  A thread loads its own segment: consecutive threads hold
+// consecutive segments, so a wave's loads cover one contiguous range.
 //
 // Partial sums are float64 per thread (on CDNA the float64 FMA issues at the
 // same rate as an unpacked float32 FMA), reduced across the wave with
 // shuffles, across the workgroup through LDS, and across workgroups by a
-// second, one-workgroup kernel that adds the per-workgroup partials in fixed
-// order with TwoSum compensation.  No float atomics: the result is
-// deterministic.  Ordering that combine behind the first kernel by the
-// stream, rather than by a device-scope fence in every workgroup (which on
-// CDNA writes back the whole L2 of the XCD), costs one short launch.
+// second, one-workgroup kernel that adds the per-workgroup partials in a
+// fixed tree.  No float atomics: the result is deterministic.  Ordering that
+// combine behind the first kernel by the stream, rather than by a
+// device-scope fence in every workgroup (which on CDNA writes back the whole
+// L2 of the XCD), costs one short launch.
 //
 // Accumulator positions: p = 0 is the inner axis (D-1), p >= 1 the outer
 // axis D-1-p, so that register arrays are indexed by compile-time positions.
@@ -132,162 +131,264 @@ __device__ __forceinline__ int64_t row_offset(const SegPlan &P, int k, const uin
     return off;
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+// Sum over the 32 lanes of a half wave (butterfly; every lane gets it).
+__device__ __forceinline__ double half_wave_sum(double v)
 {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
+    for (int o = 16; o >= 1; o >>= 1)
         v += __shfl_xor(v, o, 64);
     return v;
 }
 
-// Error-free sum (Knuth's TwoSum): s + e == a + b exactly.
-__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+// Workgroup sum of the per-thread terms acc[0..T) into dst[0..T), in a
+// fixed order.  Eight terms at a time pass through LDS transposed: thread t
+// stores its eight values at x[q][t]; then the 32 threads of half wave q sum
+// term q, each over eight stored values, and the half wave folds its 32
+// sums by shuffles.  A butterfly over all 64 lanes per term instead would
+// cost each wave 12 cross-lane reads per term, and those all queue on the
+// CU's one LDS unit.
+template <int T>
+__device__ __forceinline__ void block_sums(const double *acc, double (*x)[NT], double *dst)
 {
-    s = a + b;
-    double bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
+    static_assert(NT == 256, "eight half waves per workgroup");
+    const int tid = threadIdx.x;
+    const int q = tid >> 5, part = tid & 31;
+#pragma unroll
+    for (int i0 = 0; i0 < T; i0 += 8) {
+        __syncthreads();   // the previous chunk's reads are done
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (i0 + k < T)
+                x[k][tid] = acc[i0 + k];
+        __syncthreads();
+        double v = 0.0;
+        if (i0 + q < T) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                v += x[q][k * 32 + part];
+        }
+        v = half_wave_sum(v);
+        if (part == 0 && i0 + q < T)
+            dst[i0 + q] = v;
+    }
+    __syncthreads();
 }
 
-template <int DMAX, bool COV>
-__global__ __launch_bounds__(NT) void moments_kernel(const SegPlan P)
+// Sums of one segment of len <= SEG_MAX consecutive elements: with the
+// running sums A += w_j, B += A, C += B taken for j = 0 .. len-1,
+//   A = sum w,   B = sum w (r + 1),   C = sum w (r + 1)(r + 2) / 2,
+// where r = len - 1 - j counts from the segment's end, so that
+//   sum w r = B - A  and  sum w r^2 = 2C - 3B + A,
+// and, with e = len - 1, the sums over the local coordinate j = e - r are
+//   sum w j = e A - sum w r,   sum w j^2 = e^2 A - 2 e sum w r + sum w r^2.
+// No coordinate is ever formed per element (three float64 additions each).
+// The segment is loaded and folded in halves of HALF words (fewer live
+// registers; a row of at most HALF words never touches the second half).
+constexpr int HALF = SEG_MAX / 2;
+
+// Loads words [h0, h0 + HALF) of a segment, w = prod_k v_k.  VEC: 16-byte
+// loads (every operand contiguous along the row, len a multiple of 4);
+// else one word per element and operand.  Loads are issued unconditionally
+// (indices clamped into the segment) so that they are all in flight
+// together; the elements past len are never summed.
+// Load through the global address space, non-temporal when NTL (streamed
+// data: no reuse, and no allocation that would first have to evict lines
+// another kernel left dirty).
+typedef float f4v __attribute__((ext_vector_type(4), aligned(4)));
+
+template <bool NTL> __device__ __forceinline__ f4v ldg(const GLOBAL f4v *p)
 {
-    typedef Terms<DMAX, COV> TT;
+    if constexpr (NTL)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NTL> __device__ __forceinline__ float ldg(const GLOBAL float *p)
+{
+    if constexpr (NTL)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool VEC, bool NTL>
+__device__ __forceinline__ void seg_load_half(const SegPlan &P, const int64_t off[4], uint32_t len,
+                                              uint32_t h0, float w[HALF])
+{
+    const int n = (int)P.n;
+    if constexpr (VEC) {
+        const uint32_t qmax = (len >> 2) - 1;   // last quad of the segment
+        f4v v[HALF / 4];
+        const GLOBAL f4v *p0 =
+            (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[0] + off[0]);
+#pragma unroll
+        for (int q = 0; q < HALF / 4; ++q)
+            v[q] = ldg<NTL>(p0 + min((h0 >> 2) + (uint32_t)q, qmax));
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            if (k < n) {
+                const GLOBAL f4v *pk =
+                    (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k]);
+#pragma unroll
+                for (int q = 0; q < HALF / 4; ++q)
+                    v[q] *= ldg<NTL>(pk + min((h0 >> 2) + (uint32_t)q, qmax));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < HALF / 4; ++q) {
+            w[4 * q + 0] = v[q].x;
+            w[4 * q + 1] = v[q].y;
+            w[4 * q + 2] = v[q].z;
+            w[4 * q + 3] = v[q].w;
+        }
+    } else {
+        const int D = (int)P.D;
+        const GLOBAL float *p0 = (const GLOBAL float *)(uintptr_t)P.ptr[0] + off[0];
+        const int64_t i0 = P.stride[0][D - 1];
+#pragma unroll
+        for (int j = 0; j < HALF; ++j)
+            w[j] = ldg<NTL>(p0 + (int64_t)min(h0 + (uint32_t)j, len - 1) * i0);
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            if (k < n) {
+                const GLOBAL float *pk = (const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k];
+                const int64_t ik = P.stride[k][D - 1];
+#pragma unroll
+                for (int j = 0; j < HALF; ++j)
+                    w[j] *= ldg<NTL>(pk + (int64_t)min(h0 + (uint32_t)j, len - 1) * ik);
+            }
+        }
+    }
+}
+
+// Folds one segment whose first half w0 is already loaded (the second half,
+// when len > HALF, is loaded here).
+template <bool VEC, bool NTL, bool SECOND>
+__device__ __forceinline__ void seg_moments(const SegPlan &P, const int64_t off[4], uint32_t len,
+                                            const float w0[HALF], double &s0, double &s1,
+                                            double &s2)
+{
+    double A = 0.0, B = 0.0, C = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t h0 = (uint32_t)(h * HALF);
+        if (h == 0 || len > h0) {
+            float w1[HALF];
+            if (h == 1)
+                seg_load_half<VEC, NTL>(P, off, len, h0, w1);
+            const float *w = (h == 0) ? w0 : w1;
+#pragma unroll
+            for (int j = 0; j < HALF; ++j) {
+                if (h0 + (uint32_t)j < len) {
+                    A += (double)w[j];
+                    B += A;
+                    if (SECOND)
+                        C += B;
+                }
+            }
+        }
+    }
+    const double e = (double)len - 1.0;
+    const double r1 = B - A;
+    s0 = A;
+    s1 = fma(e, A, -r1);
+    if (SECOND) {
+        const double r2 = fma(2.0, C, fma(-3.0, B, A));
+        s2 = fma(e, fma(e, A, -2.0 * r1), r2);
+    } else {
+        s2 = 0.0;
+    }
+}
+
+// Element offsets of a segment's first element in every operand.
+template <int DM>
+__device__ __forceinline__ void seg_offsets(const SegPlan &P, const Seg &sg, int64_t off[4])
+{
+    if (P.full) {
+        const int64_t f = (int64_t)sg.row * P.L + sg.j0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            off[k] = P.base[k] + f;
+    } else {
+        const int D = (int)P.D;
+        double u[DM];
+        uint32_t tt[DM];
+        row_coords<DM>(P, sg.row, u, tt);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            off[k] = (k < (int)P.n) ? row_offset<DM>(P, k, tt) + (int64_t)sg.j0 * P.stride[k][D - 1]
+                                    : 0;
+    }
+}
+
+// Main pass: every workgroup folds tiles of NT consecutive segments, dealt
+// round-robin (the grid sweeps memory in one window), into per-thread
+// float64 accumulators [M, K_p, C_pq] over centred coordinates, then
+// reduces them across the workgroup (wave shuffles, then LDS, fixed
+// order) into one partial per term, written term-major to the workspace.
+// DM: accumulator positions (the exact number of kept axes for the
+// covariance tier; 8 or 32 for first moments only).
+// Resident workgroups per CU the register allocation aims at: 4 (128
+// VGPRs) while the accumulators leave room for the segment's 32 loaded
+// words, else 2.
+template <int DM, bool COV> constexpr int moments_min_blocks()
+{
+    return (COV ? 1 + DM + DM * (DM + 1) / 2 : 1 + DM) <= 28 ? 4 : 2;
+}
+
+template <int DM, bool COV, bool VEC, bool NTL = true>
+__global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV>())) void moments_kernel(const SegPlan P)
+{
+    typedef Terms<DM, COV> TT;
     constexpr int T = TT::T;
-    __shared__ float stage[STAGE_WORDS];
-    __shared__ double red[NT / 64][T];
+    __shared__ double xch[8][NT];
+    __shared__ double tot[T];
 
     double acc[T];
 #pragma unroll
     for (int i = 0; i < T; ++i)
         acc[i] = 0.0;
 
-    const int D = (int)P.D;
+    const int D = COV ? DM : (int)P.D;
     const double cin = P.center[D - 1];
     const uint32_t lb = seg_logical_block();
     const uint64_t g = gridDim.x;
-    const uint64_t t0 = (lb * P.ntiles) / g;
-    const uint64_t t1 = ((lb + 1) * P.ntiles) / g;
 
-    // Tile geometry: NT consecutive segments, a contiguous range of nel
-    // counter points starting at flat index f0.
-    auto geom = [&](uint64_t tile, uint64_t &s0, uint32_t &nsg, uint64_t &f0, uint32_t &nel) {
-        s0 = tile * NT;
-        nsg = (uint32_t)min((uint64_t)NT, P.nseg - s0);
-        const Seg first = seg_of(P, s0);
-        const Seg last = seg_of(P, s0 + nsg - 1);
-        f0 = seg_start(P, first);
-        nel = (uint32_t)(seg_start(P, last) + last.len - f0);
-    };
-    // Software pipeline for contiguous operands: the weights of the next
-    // tile are loaded into registers (groups of 8 independent loads, indices
-    // clamped into the tile so that no load sits behind a branch) while the
-    // current tile is folded from LDS.
-    constexpr int PRE = SEG_MAX;  // words per thread per tile (nel <= NT * SEG_MAX)
-    float pre[PRE];
-    auto load_tile = [&](uint64_t f0, uint32_t nel) {
-#pragma unroll
-        for (int gq = 0; gq < PRE / 8; ++gq) {
-            if ((uint32_t)(gq * 8 * NT) < nel) {
-                uint32_t ec[8];
-                const GLOBAL float *w0 = (const GLOBAL float *)(uintptr_t)P.ptr[0] + P.base[0] + f0;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    ec[u] = min(threadIdx.x + (uint32_t)((gq * 8 + u) * NT), nel - 1);
-                    pre[gq * 8 + u] = w0[ec[u]];
-                }
-                if (P.n > 1) {
-#pragma unroll
-                    for (int k = 1; k < 4; ++k) {
-                        if (k < (int)P.n) {
-                            const GLOBAL float *wk =
-                                (const GLOBAL float *)(uintptr_t)P.ptr[k] + P.base[k] + f0;
-#pragma unroll
-                            for (int u = 0; u < 8; ++u)
-                                pre[gq * 8 + u] *= wk[ec[u]];
-                        }
-                    }
-                }
-            }
+    for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
+        const uint64_t s = tile * NT + threadIdx.x;
+        const bool valid = s < P.nseg;
+        Seg sg{0, 0, 0};
+        int64_t off[4];
+        float w0[HALF];
+        if (valid) {
+            sg = seg_of(P, s);
+            seg_offsets<DM>(P, sg, off);
+            seg_load_half<VEC, NTL>(P, off, sg.len, 0, w0);
         }
-    };
-    if (P.full && t0 < t1) {
-        uint64_t s0, f0;
-        uint32_t nsg, nel;
-        geom(t0, s0, nsg, f0, nel);
-        load_tile(f0, nel);
-    }
-
-    for (uint64_t tile = t0; tile < t1; ++tile) {
-        uint64_t s0, f0;
-        uint32_t nsg, nel;
-        geom(tile, s0, nsg, f0, nel);
-        if (P.full) {
-            __syncthreads();               // the previous tile's reads are done
-#pragma unroll
-            for (int i = 0; i < PRE; ++i) {
-                const uint32_t e = threadIdx.x + (uint32_t)(i * NT);
-                if (e < nel)
-                    stage[sidx(e)] = pre[i];
-            }
-            __syncthreads();
-            if (tile + 1 < t1) {
-                uint64_t s0n, f0n;
-                uint32_t nsgn, neln;
-                geom(tile + 1, s0n, nsgn, f0n, neln);
-                load_tile(f0n, neln);      // in flight during the fold below
-            }
-        }
-        if (threadIdx.x < nsg) {
-            const Seg sg = seg_of(P, s0 + threadIdx.x);
-            double u[DMAX];
-            uint32_t tt[DMAX];
-            row_coords<DMAX>(P, sg.row, u, tt);
-            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-            if (P.full) {
-                const uint32_t loc = (uint32_t)(seg_start(P, sg) - f0);
-                for (uint32_t jl = 0; jl < sg.len; ++jl) {
-                    const double w = (double)stage[sidx(loc + jl)];
-                    const double x = (double)jl;
-                    r0 += w;
-                    r1 = fma(w, x, r1);
-                    r2 = fma(w * x, x, r2);
-                }
-            } else {
-                int64_t ro[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    ro[k] = (k < (int)P.n) ? row_offset<DMAX>(P, k, tt) : 0;
-                for (uint32_t jl = 0; jl < sg.len; ++jl) {
-                    const int64_t j = sg.j0 + jl;
-                    float wf = 1.0f;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (k < (int)P.n)
-                            wf *= ((const float *)(uintptr_t)P.ptr[k])[ro[k] + j * P.stride[k][D - 1]];
-                    const double w = (double)wf;
-                    const double x = (double)jl;
-                    r0 += w;
-                    r1 = fma(w, x, r1);
-                    r2 = fma(w * x, x, r2);
-                }
-            }
-            // inner axis: u_in = a + jl with a = j0 - centre
+        if (valid) {
+            double u[DM];
+            uint32_t tt[DM];
+            row_coords<DM>(P, sg.row, u, tt);
+            double s0, s1, s2;
+            seg_moments<VEC, NTL, COV>(P, off, sg.len, w0, s0, s1, s2);
+            // inner axis: u_in = a + j with a = j0 - centre
             const double a = (double)sg.j0 - cin;
-            const double A1 = fma(a, r0, r1);                       // sum w u_in
-            const double A2 = fma(a, fma(a, r0, 2.0 * r1), r2);     // sum w u_in^2
-            acc[0] += r0;
+            const double A1 = fma(a, s0, s1);                       // sum w u_in
+            acc[0] += s0;
             acc[TT::K + 0] += A1;
 #pragma unroll
-            for (int p = 1; p < DMAX; ++p)
-                acc[TT::K + p] = fma(u[p], r0, acc[TT::K + p]);
+            for (int p = 1; p < DM; ++p)
+                acc[TT::K + p] = fma(u[p], s0, acc[TT::K + p]);
             if constexpr (COV) {
+                const double A2 = fma(a, fma(a, s0, 2.0 * s1), s2);  // sum w u_in^2
                 acc[TT::c(0, 0)] += A2;
 #pragma unroll
-                for (int p = 1; p < DMAX; ++p)
+                for (int p = 1; p < DM; ++p)
                     acc[TT::c(0, p)] = fma(u[p], A1, acc[TT::c(0, p)]);
 #pragma unroll
-                for (int q = 1; q < DMAX; ++q) {
-                    const double uq = u[q] * r0;
+                for (int q = 1; q < DM; ++q) {
+                    const double uq = u[q] * s0;
 #pragma unroll
                     for (int p = 1; p <= q; ++p)
                         acc[TT::c(p, q)] = fma(u[p], uq, acc[TT::c(p, q)]);
@@ -297,107 +398,59 @@ __global__ __launch_bounds__(NT) void moments_kernel(const SegPlan P)
     }
 
     // ---- workgroup reduction (fixed order) ----
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int i = 0; i < T; ++i) {
-        double v = wave_sum(acc[i]);
-        if (lane == 0)
-            red[wave][i] = v;
-    }
-    __syncthreads();
+    block_sums<T>(acc, xch, tot);
     // Partials are term-major (term i of block b at i * nblocks + b) so the
     // combining workgroup reads them with coalesced loads.
     double *partials = (double *)((char *)(uintptr_t)P.ws + 256);
     const uint32_t nb = P.nblocks;
-    for (int i = threadIdx.x; i < T; i += NT) {
-        double v = red[0][i];
-#pragma unroll
-        for (int w = 1; w < NT / 64; ++w)
-            v += red[w][i];
-        partials[(size_t)i * nb + blockIdx.x] = v;
-    }
+    for (int i = threadIdx.x; i < T; i += NT)
+        partials[(size_t)i * nb + blockIdx.x] = tot[i];
 }
 
-// Combines the per-workgroup partials of moments_kernel (one workgroup,
-// launched right after it on the same stream: the kernel boundary makes
-// every partial visible without a device-wide cache write-back per block)
-// and writes [M, E, C] in the caller's layout.
-template <int DMAX, bool COV>
-__global__ __launch_bounds__(NT) void moments_final_kernel(const SegPlan P)
+// Combines the per-workgroup partials of moments_kernel and writes [M, E, C]
+// in the caller's layout.  One workgroup of FNT threads, launched right
+// after the main pass on the same stream (the kernel boundary makes every
+// partial visible; no device-wide fence per workgroup).  The threads form
+// 32 term slots of 32 lanes: lane l of a slot adds the partials of blocks
+// l, l + 32, ... of its term (loads issued together, in batches), then the
+// slot's half wave folds its 32 sums by shuffles.  Fixed order throughout:
+// deterministic.
+constexpr int FNT = 1024;
+
+template <int DM, bool COV>
+__global__ __launch_bounds__(FNT) void moments_final_kernel(const SegPlan P)
 {
-    typedef Terms<DMAX, COV> TT;
+    typedef Terms<DM, COV> TT;
     constexpr int T = TT::T;
-    __shared__ double red[NT / 64][T];
-    __shared__ double rc[NT / 64][T];
+    constexpr int SLOTS = FNT / 32;
+    constexpr int BATCH = 16;            // loads in flight per thread
     __shared__ double tot[T];
     __shared__ int pos_of[MAXD];
     const int D = (int)P.D;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const double *partials = (const double *)((const char *)(uintptr_t)P.ws + 256);
+    const GLOBAL double *partials = (const GLOBAL double *)((uintptr_t)P.ws + 256);
     const uint32_t nb = P.nblocks;
-    // Every thread folds blocks tid, tid + NT, ... of every term into a
-    // compensated (sum, error) pair; the pairs then meet in a fixed tree:
-    // lanes by xor-shuffles, waves in index order.  Deterministic.
-    constexpr int CH = 8;  // terms reduced together (bounds the registers)
-    constexpr int TP = (T + CH - 1) / CH * CH;  // workspace rows (padded)
+    const int slot = threadIdx.x >> 5, lane = threadIdx.x & 31;
 #pragma unroll
-    for (int i0 = 0; i0 < TP; i0 += CH) {
-        double ls[CH], lc[CH];
+    for (int i0 = 0; i0 < T; i0 += SLOTS) {
+        const int i = i0 + slot;
+        double v = 0.0;
+        if (i < T) {
+            const GLOBAL double *row = partials + (size_t)i * nb;
+            for (uint32_t b0 = 0; b0 < nb; b0 += 32 * BATCH) {
+                double x[BATCH];
 #pragma unroll
-        for (int q = 0; q < CH; ++q) {
-            ls[q] = 0.0;
-            lc[q] = 0.0;
-        }
-        for (uint32_t b0 = 0; b0 < nb; b0 += NT) {
-            // unconditional loads (clamped block index), then a select
-            const uint32_t b = b0 + threadIdx.x;
-            const bool ok = b < nb;
-            const uint32_t bc = ok ? b : 0u;
-            double v[CH];
+                for (int k = 0; k < BATCH; ++k) {
+                    const uint32_t b = b0 + (uint32_t)(k * 32 + lane);
+                    x[k] = row[b < nb ? b : 0u];
+                }
 #pragma unroll
-            for (int q = 0; q < CH; ++q)
-                v[q] = partials[(size_t)(i0 + q) * nb + bc];
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-                double e;
-                two_sum(ls[q], ok ? v[q] : 0.0, ls[q], e);
-                lc[q] += e;
+                for (int k = 0; k < BATCH; ++k)
+                    v += (b0 + (uint32_t)(k * 32 + lane) < nb) ? x[k] : 0.0;
             }
         }
-#pragma unroll
-        for (int q = 0; q < CH; ++q) {
-            const int i = i0 + q;
-            if (i >= T)
-                break;
-            double s = ls[q], c = lc[q];
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const double so = __shfl_xor(s, o, 64);
-                const double co = __shfl_xor(c, o, 64);
-                double e;
-                // (lower lane first) keeps both lanes of a pair bit-identical
-                if (lane & o)
-                    two_sum(so, s, s, e);
-                else
-                    two_sum(s, so, s, e);
-                c = (lane & o) ? (co + c) + e : (c + co) + e;
-            }
-            if (lane == 0) {
-                red[wave][i] = s;
-                rc[wave][i] = c;
-            }
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < T; i += NT) {
-        double s = red[0][i], c = rc[0][i];
-#pragma unroll
-        for (int w = 1; w < NT / 64; ++w) {
-            double e;
-            two_sum(s, red[w][i], s, e);
-            c = (c + rc[w][i]) + e;
-        }
-        tot[i] = s + c;
+        v = half_wave_sum(v);
+        if (lane == 0 && i < T)
+            tot[i] = v;
     }
     if (threadIdx.x < MAXD)
         pos_of[threadIdx.x] = -1;
@@ -416,7 +469,7 @@ __global__ __launch_bounds__(NT) void moments_final_kernel(const SegPlan P)
     const double M = tot[0];
     float *out32 = (float *)(uintptr_t)P.out32;
     double *out64 = (double *)(uintptr_t)P.out64;
-    for (int o = threadIdx.x; o < nout; o += NT) {
+    for (int o = threadIdx.x; o < nout; o += FNT) {
         double v;
         if (o == 0) {
             v = M;
@@ -592,20 +645,34 @@ __global__ __launch_bounds__(NT) void moments_adj_kernel(const SegPlan P)
 
 // ---------------------------------------------------------------------
 
+template <int DM, bool COV>
+static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
+{
+    if (L.plan.vec4)
+        hipLaunchKernelGGL((moments_kernel<DM, COV, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+    else
+        hipLaunchKernelGGL((moments_kernel<DM, COV, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+    hipLaunchKernelGGL((moments_final_kernel<DM, COV>), dim3(1), dim3(FNT), 0, st, L.plan);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments(const SegLaunch &L, hipStream_t st)
 {
     const bool cov = (L.plan.flags & TRIOT_MOMENTS_COV) != 0;
     if (cov) {
-        hipLaunchKernelGGL((moments_kernel<8, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
-        hipLaunchKernelGGL((moments_final_kernel<8, true>), dim3(1), dim3(NT), 0, st, L.plan);
-    } else if (L.dmax <= 8) {
-        hipLaunchKernelGGL((moments_kernel<8, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
-        hipLaunchKernelGGL((moments_final_kernel<8, false>), dim3(1), dim3(NT), 0, st, L.plan);
-    } else {
-        hipLaunchKernelGGL((moments_kernel<32, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
-        hipLaunchKernelGGL((moments_final_kernel<32, false>), dim3(1), dim3(NT), 0, st, L.plan);
+        switch (L.dm) {
+        case 1: return go_moments<1, true>(L, st);
+        case 2: return go_moments<2, true>(L, st);
+        case 3: return go_moments<3, true>(L, st);
+        case 4: return go_moments<4, true>(L, st);
+        case 5: return go_moments<5, true>(L, st);
+        case 6: return go_moments<6, true>(L, st);
+        case 7: return go_moments<7, true>(L, st);
+        case 8: return go_moments<8, true>(L, st);
+        default: return hipErrorInvalidValue;
+        }
     }
-    return hipGetLastError();
+    return L.dm <= 8 ? go_moments<8, false>(L, st) : go_moments<32, false>(L, st);
 }
 
 hipError_t launch_moments_adj(const SegLaunch &L, hipStream_t st)
@@ -625,35 +692,49 @@ hipError_t launch_moments_adj(const SegLaunch &L, hipStream_t st)
 
 namespace triot {
 
-// Resident workgroups per CU of the row kernels (their register and LDS
-// needs differ by tier), asked of the runtime once; 2 when no device answers.
-int segment_blocks_per_cu(bool adj, bool cov, int dmax)
+// Resident workgroups per CU of the row kernels (their register needs
+// differ by instance), asked of the runtime once per instance; 2 when no
+// device answers.
+template <class K> static int occupancy(K kernel)
 {
-    static int cache[2][2][2] = {};
-    const int a = adj ? 1 : 0, c = cov ? 1 : 0, m = dmax > 8 ? 1 : 0;
-    if (!cache[a][c][m]) {
-        int nb = 0;
-        hipError_t e;
-        if (!adj) {
-            if (cov)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_kernel<8, true>, NT, 0);
-            else if (dmax <= 8)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_kernel<8, false>, NT, 0);
-            else
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_kernel<32, false>, NT, 0);
-        } else {
-            if (cov)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_adj_kernel<8, true>, NT, 0);
-            else if (dmax <= 8)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_adj_kernel<8, false>, NT,
-                                                                 0);
-            else
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, moments_adj_kernel<32, false>,
-                                                                 NT, 0);
-        }
-        cache[a][c][m] = (e == hipSuccess && nb > 0) ? nb : 2;
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, NT, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 2;
+}
+
+template <int DM, bool COV> static int occ_moments(bool vec4)
+{
+    static int cache[2] = {0, 0};
+    int &c = cache[vec4 ? 1 : 0];
+    if (!c)
+        c = vec4 ? occupancy(moments_kernel<DM, COV, true>) : occupancy(moments_kernel<DM, COV, false>);
+    return c;
+}
+
+int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4)
+{
+    if (adj) {
+        static int cache[3] = {0, 0, 0};
+        const int i = cov ? 0 : (dm <= 8 ? 1 : 2);
+        if (!cache[i])
+            cache[i] = cov ? occupancy(moments_adj_kernel<8, true>)
+                           : (dm <= 8 ? occupancy(moments_adj_kernel<8, false>)
+                                      : occupancy(moments_adj_kernel<32, false>));
+        return cache[i];
     }
-    return cache[a][c][m];
+    if (cov) {
+        switch (dm) {
+        case 1: return occ_moments<1, true>(vec4);
+        case 2: return occ_moments<2, true>(vec4);
+        case 3: return occ_moments<3, true>(vec4);
+        case 4: return occ_moments<4, true>(vec4);
+        case 5: return occ_moments<5, true>(vec4);
+        case 6: return occ_moments<6, true>(vec4);
+        case 7: return occ_moments<7, true>(vec4);
+        default: return occ_moments<8, true>(vec4);
+        }
+    }
+    return dm <= 8 ? occ_moments<8, false>(vec4) : occ_moments<32, false>(vec4);
 }
 
 }  // namespace triot

@@ -12,6 +12,6 @@ hipError_t launch_batched(int co_op, const CoPlan *plans, const uint32_t *ustart
                           uint32_t total, int blocks, hipStream_t st);
 hipError_t launch_moments(const SegLaunch &L, hipStream_t st);
 hipError_t launch_moments_adj(const SegLaunch &L, hipStream_t st);
-int segment_blocks_per_cu(bool adj, bool cov, int dmax);
+int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4);
 
 }  // namespace triot

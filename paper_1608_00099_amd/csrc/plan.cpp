@@ -741,22 +741,38 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
         P.ptr[k] = (uint64_t)(uintptr_t)r.ptr[k];
     }
     P.full = full ? 1u : 0u;
+    // 16-byte segment loads: every operand contiguous along the row and whole
+    // quads per row (then every segment, S = min(L, 32), is whole quads too).
+    bool vec4 = (L % 4) == 0;
+    for (int k = 0; k < n; ++k)
+        if (P.stride[k][D - 1] != 1 || ((uintptr_t)r.ptr[k] % 4) != 0)
+            vec4 = false;
+    P.vec4 = vec4 ? 1u : 0u;
     const bool cov = (flags & TRIOT_MOMENTS_COV) != 0;
-    // Accumulator slots of the kernel tier: M, DMAX first sums and, with
-    // the covariance, DMAX(DMAX+1)/2 second sums (DMAX = 8 or 32).
+    // Accumulator positions of the moments pass: exactly the kept axes with
+    // the covariance (D <= 8), else a tier of 8 or 32; the adjoint keeps the
+    // tiers 8 and 32.
     const int dmax = (D <= 8) ? 8 : 32;
-    // Workspace rows per block: the slots, padded to a multiple of 8 (the
-    // final reduction reads them 8 at a time, unconditionally).
-    P.nterms = (uint32_t)((1 + dmax + (cov ? dmax * (dmax + 1) / 2 : 0) + 7) / 8 * 8);
+    const int dm = cov ? D : dmax;
+    // Workspace rows per block: M, dm first sums and, with the covariance,
+    // dm(dm+1)/2 second sums, padded to a multiple of 8 (the final
+    // reduction reads them 8 at a time, unconditionally).
+    P.nterms = (uint32_t)((1 + dm + (cov ? dm * (dm + 1) / 2 : 0) + 7) / 8 * 8);
 
-    // Persistent grid: as many workgroups as can be resident at once.
-    const int bpc = segment_blocks_per_cu(r.op == TRIOT_OP_MOMENTS_ADJ, cov, dmax);
+    // Persistent grid: as many workgroups as can be resident at once (for
+    // the moments pass at most 2 per CU: each workgroup ends in a reduction
+    // of every term, and measured on MI355X, 2 per CU beat 4).
+    const bool adj = r.op == TRIOT_OP_MOMENTS_ADJ;
+    int bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4);
+    if (!adj)
+        bpc = std::min(bpc, 2);
     int64_t blocks = std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * bpc);
     if (blocks > 8)
         blocks = (blocks + 7) / 8 * 8;
     blocks = std::max<int64_t>(blocks, 1);
     P.nblocks = (uint32_t)blocks;
     out->blocks = (int)blocks;
+    out->dm = dm;
     out->dmax = dmax;
     return TRIOT_OK;
 }

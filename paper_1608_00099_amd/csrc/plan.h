@@ -50,7 +50,9 @@ struct CoLaunch {
 struct SegLaunch {
     SegPlan plan;
     int blocks;
-    int dmax;       // register tier of the accumulators (8 or 32)
+    int dm;         // accumulator positions of the moments pass: the kept axes
+                    // with the covariance, else 8 or 32
+    int dmax;       // register tier of the adjoint (8 or 32)
 };
 
 // Number of compute units of the current device (cached per device).
