@@ -3,7 +3,9 @@
 A plain, slow, obviously-correct reference for the operations of Heyl &
 Serang, "TRIOT: Faster tensor manipulation in C++11" (arXiv 1608.00099):
 zero-pad embedding / crop copies, element-wise products over shared
-tuples, index-weighted moments (Algorithm 11) and their adjoints.  The
+tuples, index-weighted moments (Algorithm 11) and their adjoints, the
+inner product and update of benchmarks 2 and 3, marginalization, the
+nonzero bounding box and the naive convolution (Algorithms 14 and 15).  The
 arithmetic lives in ``triot_oracle.c`` (built with gcc, contraction off);
 this module only marshals numpy arrays.
 
@@ -62,6 +64,11 @@ def _configure(lib):
     lib.oracle_moments.argtypes = [I, I, P, P, P, P, I, I, P]
     lib.oracle_moments_adj.argtypes = [I, P, P, P, L, I, P, P, I]
     lib.oracle_mul_adj.argtypes = [I, P, P, P, P, P, P, P, P, I]
+    lib.oracle_dot.argtypes = [I, I, P, P, P, P, I, P]
+    lib.oracle_xpyx_mz.argtypes = [I, P, P, P, L, P, P, L, P, P, L, I]
+    lib.oracle_marginal.argtypes = [I, I, P, P, P, P, P, I, P]
+    lib.oracle_bbox.argtypes = [I, I, P, P, P, P, I, P]
+    lib.oracle_conv.argtypes = [I, P, P, P, P, P]
     return lib
 
 
@@ -251,3 +258,77 @@ def mul_adj(ga, sa, gb, sb, gout, si, a, b):
                             _ptr(_flat(a)), _ptr(_flat(b)), f64)
     _check(rc, "mul_adj")
     return ga, gb
+
+
+def _operands(counter, tensors, shapes, bases):
+    n, d = len(tensors), len(counter)
+    ptrs = (ctypes.c_void_p * n)(*[_flat(t).ctypes.data for t in tensors])
+    sh = _i64([v for s in shapes for v in s]) if d else np.zeros(1, np.int64)
+    bs = _i64(bases if bases is not None else [0] * n)
+    cc = _i64(counter) if d else np.zeros(1, np.int64)
+    return n, d, ptrs, sh, bs, cc
+
+
+def dot(counter, tensors, shapes, bases=None) -> float:
+    """sum_t prod_k v_k(t) in float64 (benchmark 2's inner product)."""
+    lib = _load()
+    f64 = _fdt(*tensors)
+    n, d, ptrs, sh, bs, cc = _operands(counter, tensors, shapes, bases)
+    out = np.zeros(1, dtype=np.float64)
+    rc = lib.oracle_dot(n, d, _ptr(cc), ptrs, _ptr(sh), _ptr(bs), f64, _ptr(out))
+    _check(rc, "dot")
+    return float(out[0])
+
+
+def xpyx_mz(counter, x, xs, y, ys, z, zs, xb=0, yb=0, zb=0):
+    """x[t] <- x[t] + y[t]*x[t] - z[t] (benchmark 3), three roundings."""
+    lib = _load()
+    f64 = _fdt(x, y, z)
+    rc = lib.oracle_xpyx_mz(len(counter), _ptr(_i64(counter)),
+                            _ptr(_flat(x)), _ptr(_i64(xs)), xb,
+                            _ptr(_flat(y)), _ptr(_i64(ys)), yb,
+                            _ptr(_flat(z)), _ptr(_i64(zs)), zb, f64)
+    _check(rc, "xpyx_mz")
+    return x
+
+
+def marginal(counter, keep, tensors, shapes, bases=None) -> np.ndarray:
+    """float64 sums of prod_k v_k(t) over the axes with keep[i] == 0; the
+    result has the kept counter extents."""
+    lib = _load()
+    f64 = _fdt(*tensors)
+    n, d, ptrs, sh, bs, cc = _operands(counter, tensors, shapes, bases)
+    kshape = tuple(int(c) for c, k in zip(counter, keep) if k)
+    out = np.zeros(max(int(np.prod(kshape, dtype=np.int64)), 1), dtype=np.float64)
+    kk = np.ascontiguousarray(np.asarray([1 if k else 0 for k in keep] or [0], dtype=np.int32))
+    rc = lib.oracle_marginal(n, d, _ptr(cc), _ptr(kk), ptrs, _ptr(sh), _ptr(bs), f64,
+                             _ptr(out))
+    _check(rc, "marginal")
+    return out[: int(np.prod(kshape, dtype=np.int64))].reshape(kshape)
+
+
+def bbox(counter, tensors, shapes, bases=None) -> np.ndarray:
+    """int64 [d, 2]: per axis, min and max t_i where every operand is
+    nonzero; all -1 when there is no such tuple."""
+    lib = _load()
+    f64 = _fdt(*tensors)
+    n, d, ptrs, sh, bs, cc = _operands(counter, tensors, shapes, bases)
+    out = np.zeros(max(2 * d, 1), dtype=np.int64)
+    rc = lib.oracle_bbox(n, d, _ptr(cc), ptrs, _ptr(sh), _ptr(bs), f64, _ptr(out))
+    _check(rc, "bbox")
+    return out[: 2 * d].reshape(d, 2)
+
+
+def conv(lhs, rhs) -> np.ndarray:
+    """Naive convolution in Algorithm 14's loop order (float64)."""
+    lib = _load()
+    assert lhs.dtype == np.float64 and rhs.dtype == np.float64
+    assert lhs.ndim == rhs.ndim
+    d = lhs.ndim
+    oshape = tuple(a + b - 1 for a, b in zip(lhs.shape, rhs.shape))
+    out = np.zeros(max(int(np.prod(oshape, dtype=np.int64)), 1), dtype=np.float64)
+    ls = _i64(lhs.shape) if d else np.zeros(1, np.int64)
+    rs = _i64(rhs.shape) if d else np.zeros(1, np.int64)
+    rc = lib.oracle_conv(d, _ptr(_flat(lhs)), _ptr(ls), _ptr(_flat(rhs)), _ptr(rs), _ptr(out))
+    _check(rc, "conv")
+    return out[: int(np.prod(oshape, dtype=np.int64))].reshape(oshape)

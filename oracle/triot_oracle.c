@@ -25,6 +25,7 @@
  * (built with -ffp-contract=off): a float32 x + y*z is two roundings.
  * Moments are accumulated in double precision in visiting order.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -501,5 +502,223 @@ int oracle_mul_adj(int d, void *ga, const int64_t *sa, void *gb,
             }
         } while (oracle_next_tuple(t, cb, d));
     }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Further tuple-visiting operations (Sections 2 and 3)                 */
+/* ------------------------------------------------------------------ */
+
+/* DOT: the inner product over the shared tuples (benchmark 2 of
+ * Section 3; Algorithm 8's captured-sum example):
+ *   out = sum_t prod_k v_k(t)    (each value widened to double),
+ * summed in double in lexicographic order. */
+int oracle_dot(int n, int d, const int64_t *counter, void *const *tensors,
+               const int64_t *shapes, const int64_t *bases, int f64,
+               double *out)
+{
+    uint64_t c[ORACLE_MAX_D], t[ORACLE_MAX_D] = {0}, npts;
+    int rc = load_counter(d, counter, c, &npts);
+    if (rc)
+        return rc;
+    if (n < 1 || n > 8)
+        return ORACLE_EINVAL;
+    operand V[8];
+    for (int k = 0; k < n; ++k) {
+        set_operand(&V[k], tensors[k], shapes + (size_t)k * d,
+                    bases ? bases[k] : 0, d, f64 ? 8 : 4);
+        if (!fits(&V[k], c, d))
+            return ORACLE_EBOUNDS;
+    }
+    double s = 0.0;
+    if (npts > 0) {
+        do {
+            double w = 1.0;
+            for (int k = 0; k < n; ++k)
+                w *= rd(at(&V[k], t, d), f64);
+            s += w;
+        } while (oracle_next_tuple(t, c, d));
+    }
+    *out = s;
+    return ORACLE_OK;
+}
+
+/* XPYX_MZ: x[t] <- x[t] + y[t]*x[t] - z[t] over the counter (benchmark 3
+ * of Section 3), evaluated as written in C: the product, then the sum,
+ * then the difference, each rounded once. */
+int oracle_xpyx_mz(int d, const int64_t *counter,
+                   void *x, const int64_t *xs, int64_t xb,
+                   const void *y, const int64_t *ys, int64_t yb,
+                   const void *z, const int64_t *zs, int64_t zb, int f64)
+{
+    uint64_t c[ORACLE_MAX_D], t[ORACLE_MAX_D] = {0}, n;
+    int rc = load_counter(d, counter, c, &n);
+    if (rc)
+        return rc;
+    size_t e = f64 ? 8 : 4;
+    operand X, Y, Z;
+    set_operand(&X, x, xs, xb, d, e);
+    set_operand(&Y, (void *)y, ys, yb, d, e);
+    set_operand(&Z, (void *)z, zs, zb, d, e);
+    if (!fits(&X, c, d) || !fits(&Y, c, d) || !fits(&Z, c, d))
+        return ORACLE_EBOUNDS;
+    if (n == 0)
+        return ORACLE_OK;
+    do {
+        if (f64) {
+            double *px = (double *)at(&X, t, d);
+            double vx = *px;
+            double vy = *(const double *)at(&Y, t, d);
+            double vz = *(const double *)at(&Z, t, d);
+            double prod = vy * vx;
+            double sum = vx + prod;
+            *px = sum - vz;
+        } else {
+            float *px = (float *)at(&X, t, d);
+            float vx = *px;
+            float vy = *(const float *)at(&Y, t, d);
+            float vz = *(const float *)at(&Z, t, d);
+            float prod = vy * vx;
+            float sum = vx + prod;
+            *px = sum - vz;
+        }
+    } while (oracle_next_tuple(t, c, d));
+    return ORACLE_OK;
+}
+
+/* MARGINAL: sum the weights w(t) = prod_k v_k(t) (double) over the axes
+ * whose keep flag is 0 (Section 2: marginalization needs the tuple).  The
+ * output is a double tensor over the kept axes (their counter extents, in
+ * axis order; a scalar when none is kept), zeroed first; every counter
+ * tuple adds its weight to the output at its kept coordinates, visiting
+ * the counter in lexicographic order. */
+int oracle_marginal(int n, int d, const int64_t *counter, const int *keep,
+                    void *const *tensors, const int64_t *shapes,
+                    const int64_t *bases, int f64, double *out)
+{
+    uint64_t c[ORACLE_MAX_D], t[ORACLE_MAX_D] = {0}, npts;
+    int rc = load_counter(d, counter, c, &npts);
+    if (rc)
+        return rc;
+    if (n < 1 || n > 8)
+        return ORACLE_EINVAL;
+    operand V[8];
+    for (int k = 0; k < n; ++k) {
+        set_operand(&V[k], tensors[k], shapes + (size_t)k * d,
+                    bases ? bases[k] : 0, d, f64 ? 8 : 4);
+        if (!fits(&V[k], c, d))
+            return ORACLE_EBOUNDS;
+    }
+    uint64_t ks[ORACLE_MAX_D], kt[ORACLE_MAX_D];
+    int dk = 0;
+    uint64_t nout = 1;
+    for (int i = 0; i < d; ++i)
+        if (keep[i]) {
+            ks[dk++] = c[i];
+            nout *= c[i];
+        }
+    for (uint64_t f = 0; f < nout; ++f)
+        out[f] = 0.0;
+    if (npts == 0)
+        return ORACLE_OK;
+    do {
+        double w = 1.0;
+        for (int k = 0; k < n; ++k)
+            w *= rd(at(&V[k], t, d), f64);
+        int j = 0;
+        for (int i = 0; i < d; ++i)
+            if (keep[i])
+                kt[j++] = t[i];
+        out[oracle_flat_index(kt, ks, dk)] += w;
+    } while (oracle_next_tuple(t, c, d));
+    return ORACLE_OK;
+}
+
+/* BBOX: the bounding box of the tuples at which every operand is nonzero
+ * (Section 2: the nonzero bounding box of an element-wise product; the
+ * product of reals is nonzero exactly when every factor is, so no
+ * floating-point product decides it; a NaN counts as nonzero).
+ * out[2i] = min t_i, out[2i+1] = max t_i over those tuples; every entry is
+ * -1 when there is none. */
+int oracle_bbox(int n, int d, const int64_t *counter, void *const *tensors,
+                const int64_t *shapes, const int64_t *bases, int f64,
+                int64_t *out)
+{
+    uint64_t c[ORACLE_MAX_D], t[ORACLE_MAX_D] = {0}, npts;
+    int rc = load_counter(d, counter, c, &npts);
+    if (rc)
+        return rc;
+    if (n < 1 || n > 8)
+        return ORACLE_EINVAL;
+    operand V[8];
+    for (int k = 0; k < n; ++k) {
+        set_operand(&V[k], tensors[k], shapes + (size_t)k * d,
+                    bases ? bases[k] : 0, d, f64 ? 8 : 4);
+        if (!fits(&V[k], c, d))
+            return ORACLE_EBOUNDS;
+    }
+    int found = 0;
+    for (int i = 0; i < d; ++i) {
+        out[2 * i] = -1;
+        out[2 * i + 1] = -1;
+    }
+    if (npts == 0)
+        return ORACLE_OK;
+    do {
+        int nz = 1;
+        for (int k = 0; k < n && nz; ++k)
+            if (!(rd(at(&V[k], t, d), f64) != 0.0))
+                nz = 0;
+        if (!nz)
+            continue;
+        for (int i = 0; i < d; ++i) {
+            int64_t v = (int64_t)t[i];
+            if (!found || v < out[2 * i])
+                out[2 * i] = v;
+            if (!found || v > out[2 * i + 1])
+                out[2 * i + 1] = v;
+        }
+        found = 1;
+    } while (oracle_next_tuple(t, c, d));
+    return ORACLE_OK;
+}
+
+/* CONV: the naive multidimensional convolution of Section 3 (Algorithms
+ * 14 and 15): result shape ls + rs - 1 on every axis, zeroed first; for
+ * every tuple t of lhs in lexicographic order and, inside, every tuple u
+ * of rhs in lexicographic order, result[t + u] += lhs[t] * rhs[u]
+ * (double, product and sum each rounded once). */
+int oracle_conv(int d, const double *lhs, const int64_t *ls, const double *rhs,
+                const int64_t *rs, double *out)
+{
+    uint64_t cl[ORACLE_MAX_D], cr[ORACLE_MAX_D], co[ORACLE_MAX_D];
+    uint64_t nl, nr, no;
+    uint64_t t[ORACLE_MAX_D] = {0}, u[ORACLE_MAX_D], v[ORACLE_MAX_D];
+    int rc = load_counter(d, ls, cl, &nl);
+    if (!rc)
+        rc = load_counter(d, rs, cr, &nr);
+    if (rc)
+        return rc;
+    for (int i = 0; i < d; ++i) {
+        if (cl[i] == 0 || cr[i] == 0)
+            return ORACLE_EINVAL;
+        co[i] = cl[i] + cr[i] - 1;
+    }
+    no = 1;
+    for (int i = 0; i < d; ++i)
+        no *= co[i];
+    for (uint64_t f = 0; f < no; ++f)
+        out[f] = 0.0;
+    do {
+        const double a = lhs[oracle_flat_index(t, cl, d)];
+        memset(u, 0, sizeof(u));
+        do {
+            for (int i = 0; i < d; ++i)
+                v[i] = t[i] + u[i];
+            double prod = a * rhs[oracle_flat_index(u, cr, d)];
+            double *o = &out[oracle_flat_index(v, co, d)];
+            *o = *o + prod;
+        } while (oracle_next_tuple(u, cr, d));
+    } while (oracle_next_tuple(t, cl, d));
     return ORACLE_OK;
 }

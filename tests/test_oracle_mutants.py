@@ -15,7 +15,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "triot_oracle.c")
 PINS = ["tests/test_oracle_index.py", "tests/test_oracle_ops.py",
-        "tests/test_oracle_moments.py", "tests/test_oracle_adjoint.py"]
+        "tests/test_oracle_moments.py", "tests/test_oracle_adjoint.py",
+        "tests/test_oracle_reductions.py"]
 
 MUTANTS = {
     "stride": ("off += t[i] * trailing;", "off += t[i] * s[i];"),
@@ -43,6 +44,18 @@ MUTANTS = {
                      "acc += gmom[1 + d + p] * dij;"),
     "mul_adj_operand": ("*(float *)dst = *(const float *)at(&GO, t, d) *\n                                    *(const float *)at(&B, t, d);",
                         "*(float *)dst = *(const float *)at(&GO, t, d) *\n                                    *(const float *)at(&A, t, d);"),
+    "dot_weight_dropped": ("            s += w;", "            s += 1.0;"),
+    "xpyx_sign": ("float sum = vx + prod;", "float sum = vx - prod;"),
+    "xpyx_operand": ("float prod = vy * vx;", "float prod = vy * vz;"),
+    "xpyx_fused": ("float prod = vy * vx;\n            float sum = vx + prod;",
+                   "float prod = 0.0f;\n            float sum = fmaf(vy, vx, vx);"),
+    "marginal_overwrite": ("out[oracle_flat_index(kt, ks, dk)] += w;",
+                           "out[oracle_flat_index(kt, ks, dk)] = w;"),
+    "bbox_max": ("if (!found || v > out[2 * i + 1])", "if (!found || v < out[2 * i + 1])"),
+    "bbox_sign": ("if (!(rd(at(&V[k], t, d), f64) != 0.0))", "if (!(rd(at(&V[k], t, d), f64) > 0.0))"),
+    "conv_correlation": ("v[i] = t[i] + u[i];", "v[i] = t[i] > u[i] ? t[i] - u[i] : u[i] - t[i];"),
+    "conv_rounding": ("double prod = a * rhs[oracle_flat_index(u, cr, d)];\n            double *o = &out[oracle_flat_index(v, co, d)];\n            *o = *o + prod;",
+                   "double prod = a * rhs[oracle_flat_index(u, cr, d)];\n            double *o = &out[oracle_flat_index(v, co, d)];\n            *o = prod + (*o + 0.0) * 1.0000000000000002;"),
 }
 
 
