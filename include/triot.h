@@ -91,9 +91,10 @@ typedef enum triot_op {
      * out (device, float32): [M, E_0..E_{d-1}] followed, with
      * TRIOT_MOMENTS_COV, by the upper triangle C_00, C_01, .., C_0(d-1),
      * C_11, .., C_(d-1)(d-1): 1 + d (+ d(d+1)/2) values.
-     * params: const triot_moments_params*.  Accumulation is float64 per
-     * thread and compensated (TwoSum) across workgroups; the result is
-     * deterministic for a given device and launch.  Needs a workspace.
+     * params: const triot_moments_params*.  Accumulation is float64 over
+     * coordinates shifted to the axis centres, summed across threads and
+     * workgroups in a fixed tree; the result is deterministic for a given
+     * device and launch.  Needs a workspace.
      * Enqueues two kernels (partial sums, then their combination).
      * Limits: the covariance needs d' <= 8 axes after dropping extent-1
      * axes (first moments: d' <= 32), and fewer than 2^32 counter rows. */
@@ -117,7 +118,42 @@ typedef enum triot_op {
      * counter tuples.  tensors[0] is the int64 output of n_tensors*N
      * values; all n shapes (including operand 0's) define offsets; the
      * other pointers are ignored.  For checking the index arithmetic. */
-    TRIOT_OP_INDEX = 7
+    TRIOT_OP_INDEX = 7,
+    /* Inner product over the shared tuples (benchmark 2 of Section 3; the
+     * captured-sum example of Algorithm 8):  out = sum_t prod_k v_k(t).
+     * tensors = {v_0, .., v_{n-1}}, float32, 1 <= n <= 4; counter NULL =
+     * the intersection.  out (device): one float32; params: optional
+     * const triot_reduce_params* (a float64 copy).  float64 accumulation,
+     * deterministic; needs a workspace; enqueues two kernels. */
+    TRIOT_OP_DOT = 8,
+    /* x[t] = (x[t] + y[t]*x[t]) - z[t] in float32 (benchmark 3 of Section
+     * 3), each operation rounded once (no fused multiply-add), over the
+     * counter (NULL = intersection).  tensors = {x, y, z}. */
+    TRIOT_OP_XPYX_MZ = 9,
+    /* Marginalization (Section 2): the sums of w(t) = prod_k v_k(t) over
+     * the counter axes NOT flagged in params->keep_mask (bit i = keep axis
+     * i).  tensors = {v_0, .., v_{n-1}}, float32, 1 <= n <= 4; counter
+     * NULL = intersection.  out (device, float32): a row-major tensor over
+     * the kept axes with their counter extents (one value when no axis is
+     * kept).  params: const triot_marginal_params* (required).  float64
+     * accumulation; deterministic; needs a workspace; two kernels. */
+    TRIOT_OP_MARGINAL = 10,
+    /* Bounding box of the tuples at which every operand is nonzero (the
+     * nonzero bounding box of an element-wise product, Section 2; a NaN
+     * counts as nonzero, +0.0 and -0.0 as zero).  tensors = {v_0, ..},
+     * float32, 1 <= n <= 4; counter NULL = intersection.  out (device,
+     * int64): [lo_0, hi_0, .., lo_{d-1}, hi_{d-1}] (inclusive), every
+     * entry -1 when no tuple qualifies.  Needs a workspace; two kernels.
+     * Limits: d' <= 32 kept axes, fewer than 2^32 counter rows. */
+    TRIOT_OP_BBOX = 11,
+    /* Naive multidimensional convolution (Algorithms 14 and 15 of Section
+     * 3): out[v] = sum over lhs tuples t (lexicographic order) with
+     * 0 <= v - t < rs of lhs[t] * rhs[v - t], float64, each product and sum
+     * rounded once; the result equals the paper's loop order bit for bit.
+     * tensors = {out, lhs, rhs}, float64; shapes = {ls + rs - 1, ls, rs}
+     * (every extent of ls and rs >= 1); counter NULL or the out shape;
+     * bases NULL or zero.  out must not overlap lhs or rhs. */
+    TRIOT_OP_CONV = 12
 } triot_op;
 
 typedef struct triot_copy_params {
@@ -131,6 +167,15 @@ typedef struct triot_moments_params {
     int flags;               /* TRIOT_MOMENTS_FIRST [| TRIOT_MOMENTS_COV] */
     double *out64;           /* optional device buffer: the same layout in float64 */
 } triot_moments_params;
+
+typedef struct triot_reduce_params {
+    double *out64;           /* optional device buffer: the result in float64 */
+} triot_reduce_params;
+
+typedef struct triot_marginal_params {
+    uint32_t keep_mask;      /* bit i set: counter axis i is kept in the output */
+    double *out64;           /* optional device buffer: the result in float64 */
+} triot_marginal_params;
 
 typedef struct triot_moments_adj_params {
     int flags;               /* TRIOT_MOMENTS_COV: gmom carries gC */

@@ -21,7 +21,8 @@ STATUS_NAMES = ["OK", "E_INVALID", "E_DIM", "E_BOUNDS", "E_ALIAS", "E_OVERFLOW",
                 "E_DEVICE", "E_UNSUPPORTED"]
 
 # triot_op
-OP_COPY, OP_EMBED_FILL, OP_MUL_ACC, OP_MUL, OP_MOMENTS, OP_MOMENTS_ADJ, OP_MUL_ADJ, OP_INDEX = range(8)
+(OP_COPY, OP_EMBED_FILL, OP_MUL_ACC, OP_MUL, OP_MOMENTS, OP_MOMENTS_ADJ, OP_MUL_ADJ, OP_INDEX,
+ OP_DOT, OP_XPYX_MZ, OP_MARGINAL, OP_BBOX, OP_CONV) = range(13)
 
 MOMENTS_FIRST = 1
 MOMENTS_COV = 2
@@ -33,6 +34,14 @@ class CopyParams(ctypes.Structure):
 
 class MomentsParams(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_int), ("out64", ctypes.c_void_p)]
+
+
+class ReduceParams(ctypes.Structure):
+    _fields_ = [("out64", ctypes.c_void_p)]
+
+
+class MarginalParams(ctypes.Structure):
+    _fields_ = [("keep_mask", ctypes.c_uint32), ("out64", ctypes.c_void_p)]
 
 
 class MomentsAdjParams(ctypes.Structure):

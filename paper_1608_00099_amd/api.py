@@ -205,6 +205,83 @@ def moments_adj(shape, mom64, gmom32, cov=True, device=None):
     return g
 
 
+# ---------------------------------------------------------------------------
+# Benchmarks 2-4 of Section 3 and the tuple-reading reductions of Section 2
+# ---------------------------------------------------------------------------
+
+def dot(a, b, *others, counter=None):
+    """(out32, out64): sum_t a[t] * b[t] * ... over the shared tuples
+    (benchmark 2's inner product), float64 accumulation."""
+    tensors = [a, b] + list(others)
+    _f32(*tensors)
+    dev, shapes = _prep(tensors, None)
+    out32 = torch.empty(1, dtype=torch.float32, device=dev)
+    out64 = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = workspace_for(L.OP_DOT, shapes, counter, dev)
+    apply(L.OP_DOT, tensors, shapes, counter, None, L.ReduceParams(out64.data_ptr()), out=out32,
+          workspace=ws, what="dot")
+    return out32, out64
+
+
+def xpyx_mz_(x, y, z, counter=None, shapes=None, bases=None):
+    """x[t] = (x[t] + y[t]*x[t]) - z[t] over counter (default: the
+    intersection; benchmark 3), three roundings."""
+    _f32(x, y, z)
+    apply(L.OP_XPYX_MZ, [x, y, z], shapes, counter, bases, what="xpyx_mz")
+    return x
+
+
+def marginal(p, keep, others=(), counter=None):
+    """(out32, out64): sums of w(t) = p[t] * prod(others[k][t]) over the
+    counter axes whose keep flag is false; the result has the kept
+    counter extents."""
+    tensors = [p] + list(others)
+    _f32(*tensors)
+    dev, shapes = _prep(tensors, None)
+    d = p.dim()
+    if counter is None:
+        counter = tuple(min(s[i] for s in shapes) for i in range(d))
+    kshape = tuple(int(c) for c, k in zip(counter, keep) if k)
+    mask = 0
+    for i, k in enumerate(keep):
+        if k:
+            mask |= 1 << i
+    out32 = torch.empty(kshape, dtype=torch.float32, device=dev)
+    out64 = torch.empty(kshape, dtype=torch.float64, device=dev)
+    ws = workspace_for(L.OP_MARGINAL, shapes, counter, dev)
+    apply(L.OP_MARGINAL, tensors, shapes, counter, None, L.MarginalParams(mask, out64.data_ptr()),
+          out=out32, workspace=ws, what="marginal")
+    return out32, out64
+
+
+def bbox(p, *others, counter=None):
+    """int64 [d, 2]: per axis, the least and greatest t_i at which every
+    operand is nonzero (all -1 when there is none)."""
+    tensors = [p] + list(others)
+    _f32(*tensors)
+    dev, shapes = _prep(tensors, None)
+    d = p.dim()
+    out = torch.empty((d, 2), dtype=torch.int64, device=dev)
+    ws = workspace_for(L.OP_BBOX, shapes, counter, dev)
+    apply(L.OP_BBOX, tensors, shapes, counter, None, None, out=out, workspace=ws, what="bbox")
+    return out
+
+
+def conv(lhs, rhs, out=None):
+    """Naive convolution (Algorithms 14 and 15), float64, result shape
+    lhs.shape + rhs.shape - 1, equal to the paper's loop order bit for bit."""
+    if lhs.dtype != torch.float64 or rhs.dtype != torch.float64:
+        raise ValueError("conv takes float64 tensors")
+    if lhs.dim() != rhs.dim():
+        raise ValueError("conv operands must have the same dimension")
+    oshape = tuple(a + b - 1 for a, b in zip(lhs.shape, rhs.shape))
+    if out is None:
+        out = torch.empty(oshape, dtype=torch.float64, device=lhs.device)
+    apply(L.OP_CONV, [out, lhs.contiguous(), rhs.contiguous()],
+          [oshape, tuple(lhs.shape), tuple(rhs.shape)], None, None, None, what="conv")
+    return out
+
+
 def index(shapes, counter=None, bases=None, device="cuda"):
     """int64 [n, N]: the offset of every counter tuple in every operand."""
     shapes = [tuple(int(v) for v in s) for s in shapes]
@@ -311,7 +388,8 @@ def describe(op, shapes, counter=None, ptrs=None, bases=None, params=None):
             "high_axes": info.high_axes, "low_axes": info.low_axes, "box_rows": info.box_rows,
             "units": info.units, "blocks": info.blocks, "threads": info.threads,
             "unroll": info.unroll, "inner_unit": info.inner_unit,
-            "cache_policy": info.cache_policy, "unit_order": info.unit_order}
+            "cache_policy": info.cache_policy, "unit_order": info.unit_order,
+            "n_tensors": len(shapes)}
 
 
 _CO_OP = {0: 0, 1: 1, 2: 2, 3: 3, 6: 4, 7: 5}   # public op -> kernel template op
@@ -326,7 +404,9 @@ def kernel_name(op, plan):
         if op == L.OP_MOMENTS:
             dm = plan["dims"] if plan.get("cov") else dmax
             vec = "true" if plan["vec"] == 4 else "false"
-            return "void triot::moments_kernel<%d, %s, %s>(triot::SegPlan)" % (dm, cov, vec)
+            multi = "true" if plan.get("n_tensors", 1) > 1 else "false"
+            return "void triot::moments_kernel<%d, %s, %s, %s, true>(triot::SegPlan)" % (
+                dm, cov, vec, multi)
         return "void triot::moments_adj_kernel<%d, %s>(triot::SegPlan)" % (dmax, cov)
     rows1 = "true" if plan["box_rows"] == 1 else "false"
     unit = "true" if plan["inner_unit"] else "false"

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtriot.so")
-SOURCES = ["plan.cpp", "api.cpp", "kern_coiter.hip", "kern_segment.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "kern_coiter.hip", "kern_segment.hip", "kern_reduce.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -29,6 +29,7 @@ int co_op_of(triot_op op)
     case TRIOT_OP_MUL: return CO_MUL;
     case TRIOT_OP_MUL_ADJ: return CO_MUL_ADJ;
     case TRIOT_OP_INDEX: return CO_INDEX;
+    case TRIOT_OP_XPYX_MZ: return CO_XPYX_MZ;
     default: return -1;
     }
 }
@@ -140,10 +141,44 @@ triot_status run_request(const Request &r, const Sched &s, void *out, void *work
             L.plan.ws = (uint64_t)(uintptr_t)workspace;
             return to_status(launch_moments(L, stream));
         }
+        if (r.op == TRIOT_OP_DOT || r.op == TRIOT_OP_BBOX) {
+            if (!out)
+                return TRIOT_E_INVALID;
+            if (!workspace || workspace_bytes < segment_workspace_bytes(L))
+                return TRIOT_E_WORKSPACE;
+            L.plan.out32 = (uint64_t)(uintptr_t)out;
+            L.plan.out64 = (r.op == TRIOT_OP_DOT && r.params)
+                               ? (uint64_t)(uintptr_t)((const triot_reduce_params *)r.params)->out64
+                               : 0;
+            L.plan.ws = (uint64_t)(uintptr_t)workspace;
+            return to_status(r.op == TRIOT_OP_DOT ? launch_dot(L, stream) : launch_bbox(L, stream));
+        }
         const triot_moments_adj_params *p = (const triot_moments_adj_params *)r.params;
         L.plan.out64 = (uint64_t)(uintptr_t)p->mom;
         L.plan.gmom = (uint64_t)(uintptr_t)p->gmom;
         return to_status(launch_moments_adj(L, stream));
+    }
+    if (r.op == TRIOT_OP_CONV) {
+        ConvLaunch L;
+        triot_status st = plan_conv(r, &L);
+        if (st != TRIOT_OK)
+            return st;
+        return to_status(launch_conv(L, stream));
+    }
+    if (r.op == TRIOT_OP_MARGINAL) {
+        if (!out)
+            return TRIOT_E_INVALID;
+        MargLaunch L;
+        triot_status st = plan_marginal(r, cus, &L);
+        if (st != TRIOT_OK)
+            return st;
+        if (L.plan.parts > 1 && (!workspace || workspace_bytes < marginal_workspace_bytes(cus)))
+            return TRIOT_E_WORKSPACE;
+        const triot_marginal_params *mp = (const triot_marginal_params *)r.params;
+        L.plan.out32 = (uint64_t)(uintptr_t)out;
+        L.plan.out64 = (uint64_t)(uintptr_t)mp->out64;
+        L.plan.ws = (uint64_t)(uintptr_t)workspace;
+        return to_status(launch_marginal(L, stream));
     }
     CoLaunch L;
     triot_status st = plan_coiter(r, s, cus, &L);
@@ -172,14 +207,20 @@ extern "C" triot_status triot_apply(triot_op op, int n_tensors, int d, const int
 extern "C" size_t triot_workspace_size(triot_op op, int n_tensors, int d, const int64_t *shapes,
                                        const int64_t *counter_shape)
 {
-    if (op != TRIOT_OP_MOMENTS)
+    if (op == TRIOT_OP_MARGINAL)
+        return marginal_workspace_bytes(device_cus());
+    if (op != TRIOT_OP_MOMENTS && op != TRIOT_OP_DOT && op != TRIOT_OP_BBOX)
         return 0;
     void *dummy[TRIOT_MAX_TENSORS];
     for (int k = 0; k < TRIOT_MAX_TENSORS; ++k)
-        dummy[k] = (void *)(uintptr_t)256;
+        dummy[k] = (void *)(uintptr_t)(256 + (1ull << 40) * k);
     Request r;
     if (validate(op, n_tensors, d, shapes, counter_shape, dummy, nullptr, nullptr, &r) != TRIOT_OK)
         return 0;
+    if (op != TRIOT_OP_MOMENTS) {
+        SegLaunch L;
+        return plan_segment(r, device_cus(), &L) == TRIOT_OK ? segment_workspace_bytes(L) : 0;
+    }
     // Enough for either tier (first moments only, or with the covariance).
     triot_moments_params mp;
     mp.out64 = nullptr;
@@ -252,6 +293,38 @@ extern "C" triot_status triot_plan_describe(triot_op op, int n_tensors, int d, c
         info->unroll = 1;
         return TRIOT_OK;
     }
+    if (op == TRIOT_OP_CONV) {
+        ConvLaunch L;
+        st = plan_conv(r, &L);
+        if (st != TRIOT_OK)
+            return st;
+        info->kernel = 2;
+        info->dims = (int)L.plan.d;
+        for (int i = 0; i < (int)L.plan.d; ++i)
+            info->extents[i] = r.shape[0][i];
+        info->vec = L.plan.lds ? 1 : 0;       // 1: inputs staged in LDS
+        info->units = (int64_t)L.plan.nout;
+        info->blocks = (int)((L.plan.nout + 255) / 256);
+        info->threads = 256;
+        info->unroll = 1;
+        return TRIOT_OK;
+    }
+    if (op == TRIOT_OP_MARGINAL) {
+        MargLaunch L;
+        st = plan_marginal(r, cus, &L);
+        if (st != TRIOT_OK)
+            return st;
+        info->kernel = 3;
+        info->dims = (int)(L.plan.dk + L.plan.dr);
+        info->high_axes = (int)L.plan.dk;     // kept axes
+        info->low_axes = (int)L.plan.dr;      // reduced axes
+        info->box_rows = (int64_t)L.plan.parts;
+        info->units = (int64_t)(L.plan.nout * L.plan.parts);
+        info->blocks = (int)((info->units + 255) / 256);
+        info->threads = 256;
+        info->unroll = 1;
+        return TRIOT_OK;
+    }
     CoLaunch L;
     st = plan_coiter(r, sched_for(r), cus, &L);
     if (st != TRIOT_OK)
@@ -298,8 +371,8 @@ extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const 
     triot_status st = validate(op, n_tensors, d, shapes, counter_shape, tensors, bases, params, &r);
     if (st != TRIOT_OK)
         return st;
-    if (r.npoints == 0 || is_segment_op(op))
-        return TRIOT_OK;  // nothing to choose: the row kernels have one schedule
+    if (r.npoints == 0 || co_op_of(op) < 0)
+        return TRIOT_OK;  // nothing to choose: the other kernels have one schedule
     hipEvent_t ev0, ev1;
     if (hipEventCreate(&ev0) != hipSuccess)
         return TRIOT_E_DEVICE;
@@ -412,7 +485,7 @@ extern "C" triot_status triot_schedule_set(triot_op op, int n_tensors, int d,
     triot_status st = validate(op, n_tensors, d, shapes, counter_shape, tensors, bases, params, &r);
     if (st != TRIOT_OK)
         return st;
-    if (is_segment_op(op))
+    if (co_op_of(op) < 0)
         return TRIOT_E_UNSUPPORTED;
     Sched s;
     s.vec_max = schedule->vec_max;

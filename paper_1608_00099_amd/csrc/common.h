@@ -27,6 +27,7 @@ enum CoOp : int {
     CO_MUL = 3,
     CO_MUL_ADJ = 4,
     CO_INDEX = 5,
+    CO_XPYX_MZ = 6,
 };
 
 // Division of a 32-bit n by an invariant divisor c >= 2 (Granlund &
@@ -118,6 +119,36 @@ struct SegPlan {
     uint64_t out64;           // MOMENTS: optional double results; ADJ: moments in
     uint64_t gmom;            // ADJ: float partials
     uint64_t ws;              // MOMENTS: partials + ticket
+};
+
+// ---------------------------------------------------------------------
+// Naive convolution plan (one thread per output element).
+struct ConvPlan {
+    uint32_t d;
+    uint32_t lds;             // 1: both inputs staged in LDS
+    uint64_t nout;            // output elements (< 2^32)
+    uint32_t nl, nr;          // input elements (LDS staging sizes)
+    AxisDiv ax[MAXD];         // output extents (axes 1..d-1 divided)
+    uint32_t ls[MAXD], rs[MAXD];
+    int64_t lstride[MAXD], rstride[MAXD];
+    uint64_t out, lhs, rhs;   // device addresses (float64)
+};
+
+// ---------------------------------------------------------------------
+// Marginalization plan: thread (o, p) sums part p of the reduced sub-box
+// of kept tuple o; a second pass adds the parts in order when parts > 1.
+struct MargPlan {
+    uint32_t n, dk, dr;       // operands, kept axes, reduced axes
+    uint32_t parts;
+    uint64_t nout;            // kept tuples (< 2^32)
+    uint64_t nred;            // reduced tuples
+    AxisDiv kax[MAXD];        // kept extents, outermost first
+    AxisDiv rax[MAXD];        // reduced extents, outermost first
+    int64_t kstride[4][MAXD]; // element strides of the kept axes per operand
+    int64_t rstride[4][MAXD]; // element strides of the reduced axes per operand
+    int64_t base[4];
+    uint64_t ptr[4];
+    uint64_t out32, out64, ws;
 };
 
 // Host-side helpers (plan.cpp).

@@ -138,6 +138,7 @@ template <> struct OpInfo<CO_MUL_ACC> { static constexpr int N = 3; static const
 template <> struct OpInfo<CO_MUL> { static constexpr int N = 3; static constexpr bool PRED = false; };
 template <> struct OpInfo<CO_MUL_ADJ> { static constexpr int N = 5; static constexpr bool PRED = true; };
 template <> struct OpInfo<CO_INDEX> { static constexpr int N = MAXT; static constexpr bool PRED = false; };
+template <> struct OpInfo<CO_XPYX_MZ> { static constexpr int N = 3; static constexpr bool PRED = false; };
 
 // Process one work unit (a part of one box).
 template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP>
@@ -305,6 +306,23 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                 if (valid[u]) {
                     VF prod = y[u] * z[u];       // rounded once (no contraction)
                     gstore<VF, CP>(bp[0], off[0][u], x[u] + prod);
+                }
+        } else if constexpr (OP == CO_XPYX_MZ) {
+            VF x[U], y[U], z[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u]) {
+                    x[u] = gload<VF, CP>(bp[0], off[0][u]);
+                    y[u] = gload<VF, CP>(bp[1], off[1][u]);
+                    z[u] = gload<VF, CP>(bp[2], off[2][u]);
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u]) {
+                    // (x + y*x) - z, each operation rounded once
+                    VF prod = y[u] * x[u];
+                    VF sum = x[u] + prod;
+                    gstore<VF, CP>(bp[0], off[0][u], sum - z[u]);
                 }
         } else if constexpr (OP == CO_MUL) {
             VF a[U], b[U];
@@ -506,6 +524,7 @@ hipError_t launch_coiter(int co_op, const CoLaunch &L, hipStream_t st)
     case CO_MUL_ACC: return pick_cache<CO_MUL_ACC>(L, st);
     case CO_MUL: return pick_cache<CO_MUL>(L, st);
     case CO_MUL_ADJ: return pick_cache<CO_MUL_ADJ>(L, st);
+    case CO_XPYX_MZ: return pick_cache<CO_XPYX_MZ>(L, st);
     case CO_INDEX: return pick_vec<CO_INDEX, CP_NORMAL>(L, st);
     default: return hipErrorInvalidValue;
     }

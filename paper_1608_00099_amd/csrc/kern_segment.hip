@@ -186,16 +186,11 @@ __device__ __forceinline__ void block_sums(const double *acc, double (*x)[NT], d
 // registers; a row of at most HALF words never touches the second half).
 constexpr int HALF = SEG_MAX / 2;
 
-// Loads words [h0, h0 + HALF) of a segment, w = prod_k v_k.  VEC: 16-byte
-// loads (every operand contiguous along the row, len a multiple of 4);
-// else one word per element and operand.  Loads are issued unconditionally
-// (indices clamped into the segment) so that they are all in flight
-// together; the elements past len are never summed.
+typedef float f4v __attribute__((ext_vector_type(4), aligned(4)));
+
 // Load through the global address space, non-temporal when NTL (streamed
 // data: no reuse, and no allocation that would first have to evict lines
 // another kernel left dirty).
-typedef float f4v __attribute__((ext_vector_type(4), aligned(4)));
-
 template <bool NTL> __device__ __forceinline__ f4v ldg(const GLOBAL f4v *p)
 {
     if constexpr (NTL)
@@ -212,51 +207,68 @@ template <bool NTL> __device__ __forceinline__ float ldg(const GLOBAL float *p)
         return *p;
 }
 
+// Weights of a half segment: float words for one operand; with several
+// operands (MULTI) their product, formed in float64 in operand order (the
+// definition's w = prod_k v_k; a float32 product would round).
+template <bool MULTI> struct HalfW {
+    float w[HALF];
+    __device__ __forceinline__ double at(int j) const { return (double)w[j]; }
+};
+template <> struct HalfW<true> {
+    double w[HALF];
+    __device__ __forceinline__ double at(int j) const { return w[j]; }
+};
+
+// Loads words [h0, h0 + HALF) of a segment of every operand.  VEC: 16-byte
+// loads (every operand contiguous along the row, len a multiple of 4);
+// else one word per element and operand.  Loads are issued
+// unconditionally (indices clamped into the segment) so that they are all
+// in flight together; the elements past len are never summed.
 template <bool VEC, bool NTL>
-__device__ __forceinline__ void seg_load_half(const SegPlan &P, const int64_t off[4], uint32_t len,
-                                              uint32_t h0, float w[HALF])
+__device__ __forceinline__ void load_words(const SegPlan &P, int k, const int64_t off[4],
+                                           uint32_t len, uint32_t h0, float v[HALF])
 {
-    const int n = (int)P.n;
     if constexpr (VEC) {
         const uint32_t qmax = (len >> 2) - 1;   // last quad of the segment
-        f4v v[HALF / 4];
-        const GLOBAL f4v *p0 =
-            (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[0] + off[0]);
-#pragma unroll
-        for (int q = 0; q < HALF / 4; ++q)
-            v[q] = ldg<NTL>(p0 + min((h0 >> 2) + (uint32_t)q, qmax));
-#pragma unroll
-        for (int k = 1; k < 4; ++k) {
-            if (k < n) {
-                const GLOBAL f4v *pk =
-                    (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k]);
-#pragma unroll
-                for (int q = 0; q < HALF / 4; ++q)
-                    v[q] *= ldg<NTL>(pk + min((h0 >> 2) + (uint32_t)q, qmax));
-            }
-        }
+        const GLOBAL f4v *pk =
+            (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k]);
 #pragma unroll
         for (int q = 0; q < HALF / 4; ++q) {
-            w[4 * q + 0] = v[q].x;
-            w[4 * q + 1] = v[q].y;
-            w[4 * q + 2] = v[q].z;
-            w[4 * q + 3] = v[q].w;
+            const f4v x = ldg<NTL>(pk + min((h0 >> 2) + (uint32_t)q, qmax));
+            v[4 * q + 0] = x.x;
+            v[4 * q + 1] = x.y;
+            v[4 * q + 2] = x.z;
+            v[4 * q + 3] = x.w;
         }
     } else {
         const int D = (int)P.D;
-        const GLOBAL float *p0 = (const GLOBAL float *)(uintptr_t)P.ptr[0] + off[0];
-        const int64_t i0 = P.stride[0][D - 1];
+        const GLOBAL float *pk = (const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k];
+        const int64_t ik = P.stride[k][D - 1];
 #pragma unroll
         for (int j = 0; j < HALF; ++j)
-            w[j] = ldg<NTL>(p0 + (int64_t)min(h0 + (uint32_t)j, len - 1) * i0);
+            v[j] = ldg<NTL>(pk + (int64_t)min(h0 + (uint32_t)j, len - 1) * ik);
+    }
+}
+
+template <bool VEC, bool NTL, bool MULTI>
+__device__ __forceinline__ void seg_load_half(const SegPlan &P, const int64_t off[4], uint32_t len,
+                                              uint32_t h0, HalfW<MULTI> &W)
+{
+    if constexpr (!MULTI) {
+        load_words<VEC, NTL>(P, 0, off, len, h0, W.w);
+    } else {
+        float v[HALF];
+        load_words<VEC, NTL>(P, 0, off, len, h0, v);
+#pragma unroll
+        for (int j = 0; j < HALF; ++j)
+            W.w[j] = (double)v[j];
 #pragma unroll
         for (int k = 1; k < 4; ++k) {
-            if (k < n) {
-                const GLOBAL float *pk = (const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k];
-                const int64_t ik = P.stride[k][D - 1];
+            if (k < (int)P.n) {
+                load_words<VEC, NTL>(P, k, off, len, h0, v);
 #pragma unroll
                 for (int j = 0; j < HALF; ++j)
-                    w[j] *= ldg<NTL>(pk + (int64_t)min(h0 + (uint32_t)j, len - 1) * ik);
+                    W.w[j] *= (double)v[j];
             }
         }
     }
@@ -264,25 +276,27 @@ __device__ __forceinline__ void seg_load_half(const SegPlan &P, const int64_t of
 
 // Folds one segment whose first half w0 is already loaded (the second half,
 // when len > HALF, is loaded here).
-template <bool VEC, bool NTL, bool SECOND>
+// ORDER: 0 the mass only, 1 with the first sum, 2 with the second too.
+template <bool VEC, bool NTL, bool MULTI, int ORDER>
 __device__ __forceinline__ void seg_moments(const SegPlan &P, const int64_t off[4], uint32_t len,
-                                            const float w0[HALF], double &s0, double &s1,
+                                            const HalfW<MULTI> &w0, double &s0, double &s1,
                                             double &s2)
 {
+    constexpr bool SECOND = ORDER >= 2;
     double A = 0.0, B = 0.0, C = 0.0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const uint32_t h0 = (uint32_t)(h * HALF);
         if (h == 0 || len > h0) {
-            float w1[HALF];
+            HalfW<MULTI> w1;
             if (h == 1)
-                seg_load_half<VEC, NTL>(P, off, len, h0, w1);
-            const float *w = (h == 0) ? w0 : w1;
+                seg_load_half<VEC, NTL, MULTI>(P, off, len, h0, w1);
 #pragma unroll
             for (int j = 0; j < HALF; ++j) {
                 if (h0 + (uint32_t)j < len) {
-                    A += (double)w[j];
-                    B += A;
+                    A += (h == 0) ? w0.at(j) : w1.at(j);
+                    if (ORDER >= 1)
+                        B += A;
                     if (SECOND)
                         C += B;
                 }
@@ -332,13 +346,13 @@ __device__ __forceinline__ void seg_offsets(const SegPlan &P, const Seg &sg, int
 // Resident workgroups per CU the register allocation aims at: 4 (128
 // VGPRs) while the accumulators leave room for the segment's 32 loaded
 // words, else 2.
-template <int DM, bool COV> constexpr int moments_min_blocks()
+template <int DM, bool COV, bool MULTI> constexpr int moments_min_blocks()
 {
-    return (COV ? 1 + DM + DM * (DM + 1) / 2 : 1 + DM) <= 28 ? 4 : 2;
+    return (!MULTI && (COV ? 1 + DM + DM * (DM + 1) / 2 : 1 + DM) <= 28) ? 4 : 2;
 }
 
-template <int DM, bool COV, bool VEC, bool NTL = true>
-__global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV>())) void moments_kernel(const SegPlan P)
+template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true>
+__global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void moments_kernel(const SegPlan P)
 {
     typedef Terms<DM, COV> TT;
     constexpr int T = TT::T;
@@ -360,18 +374,18 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV>())) void moments_k
         const bool valid = s < P.nseg;
         Seg sg{0, 0, 0};
         int64_t off[4];
-        float w0[HALF];
+        HalfW<MULTI> w0;
         if (valid) {
             sg = seg_of(P, s);
             seg_offsets<DM>(P, sg, off);
-            seg_load_half<VEC, NTL>(P, off, sg.len, 0, w0);
+            seg_load_half<VEC, NTL, MULTI>(P, off, sg.len, 0, w0);
         }
         if (valid) {
             double u[DM];
             uint32_t tt[DM];
             row_coords<DM>(P, sg.row, u, tt);
             double s0, s1, s2;
-            seg_moments<VEC, NTL, COV>(P, off, sg.len, w0, s0, s1, s2);
+            seg_moments<VEC, NTL, MULTI, COV ? 2 : 1>(P, off, sg.len, w0, s0, s1, s2);
             // inner axis: u_in = a + j with a = j0 - centre
             const double a = (double)sg.j0 - cin;
             const double A1 = fma(a, s0, s1);                       // sum w u_in
@@ -644,14 +658,254 @@ __global__ __launch_bounds__(NT) void moments_adj_kernel(const SegPlan P)
 }
 
 // ---------------------------------------------------------------------
+// Inner product (benchmark 2 of Section 3): the mass of the weights alone,
+// through the same segments, loads and fixed-order reductions.
+// ---------------------------------------------------------------------
+template <int DM, bool VEC, bool MULTI, bool NTL = true>
+__global__ __launch_bounds__(NT, 4) void dot_kernel(const SegPlan P)
+{
+    __shared__ double xch[8][NT];
+    __shared__ double tot[1];
+    double acc[1] = {0.0};
+    const uint32_t lb = seg_logical_block();
+    const uint64_t g = gridDim.x;
+    for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
+        const uint64_t s = tile * NT + threadIdx.x;
+        if (s < P.nseg) {
+            const Seg sg = seg_of(P, s);
+            int64_t off[4];
+            HalfW<MULTI> w0;
+            seg_offsets<DM>(P, sg, off);
+            seg_load_half<VEC, NTL, MULTI>(P, off, sg.len, 0, w0);
+            double s0, s1, s2;
+            seg_moments<VEC, NTL, MULTI, 0>(P, off, sg.len, w0, s0, s1, s2);
+            acc[0] += s0;
+        }
+    }
+    block_sums<1>(acc, xch, tot);
+    if (threadIdx.x == 0)
+        ((double *)((char *)(uintptr_t)P.ws + 256))[blockIdx.x] = tot[0];
+}
+
+// Sum of the per-workgroup partials (32 lanes, fixed order), written as
+// float32 to out32[0] and, when requested, float64 to out64[0].
+__global__ __launch_bounds__(64) void dot_final_kernel(const SegPlan P)
+{
+    const GLOBAL double *partials = (const GLOBAL double *)((uintptr_t)P.ws + 256);
+    const uint32_t nb = P.nblocks;
+    const int lane = threadIdx.x & 31;
+    double v = 0.0;
+    if (threadIdx.x < 32)
+        for (uint32_t b = lane; b < nb; b += 32)
+            v += partials[b];
+    v = half_wave_sum(v);
+    if (threadIdx.x == 0) {
+        ((float *)(uintptr_t)P.out32)[0] = (float)v;
+        if (P.out64)
+            ((double *)(uintptr_t)P.out64)[0] = v;
+    }
+}
+
+// ---------------------------------------------------------------------
+// Nonzero bounding box (Section 2): per counter position, the least and
+// greatest digit at which every operand is nonzero.  Each operand is
+// compared with zero separately (a float32 product of nonzero values may
+// underflow to zero; the reals' product is nonzero exactly when every
+// factor is).  Per segment a bit mask of the qualifying elements gives the
+// inner extent; the outer digits enter once per segment.  Minima and
+// maxima do not depend on the order of combination: LDS atomics fold the
+// workgroup, a second kernel the workgroups.  hi is kept as digit + 1 so
+// that 0 means "none".
+// ---------------------------------------------------------------------
+template <bool VEC, bool NTL>
+__device__ __forceinline__ uint32_t seg_nonzero_half(const SegPlan &P, const int64_t off[4],
+                                                     uint32_t len, uint32_t h0)
+{
+    const int n = (int)P.n;
+    uint32_t m = 0xFFFFu;
+    if constexpr (VEC) {
+        const uint32_t qmax = (len >> 2) - 1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < n) {
+                const GLOBAL f4v *pk =
+                    (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k]);
+                f4v v[HALF / 4];
+#pragma unroll
+                for (int q = 0; q < HALF / 4; ++q)
+                    v[q] = ldg<NTL>(pk + min((h0 >> 2) + (uint32_t)q, qmax));
+                uint32_t mk = 0;
+#pragma unroll
+                for (int q = 0; q < HALF / 4; ++q) {
+                    mk |= (v[q].x != 0.0f ? 1u : 0u) << (4 * q + 0);
+                    mk |= (v[q].y != 0.0f ? 1u : 0u) << (4 * q + 1);
+                    mk |= (v[q].z != 0.0f ? 1u : 0u) << (4 * q + 2);
+                    mk |= (v[q].w != 0.0f ? 1u : 0u) << (4 * q + 3);
+                }
+                m &= mk;
+            }
+        }
+    } else {
+        const int D = (int)P.D;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k < n) {
+                const GLOBAL float *pk = (const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k];
+                const int64_t ik = P.stride[k][D - 1];
+                float v[HALF];
+#pragma unroll
+                for (int j = 0; j < HALF; ++j)
+                    v[j] = ldg<NTL>(pk + (int64_t)min(h0 + (uint32_t)j, len - 1) * ik);
+                uint32_t mk = 0;
+#pragma unroll
+                for (int j = 0; j < HALF; ++j)
+                    mk |= (v[j] != 0.0f ? 1u : 0u) << j;
+                m &= mk;
+            }
+        }
+    }
+    // keep only the elements of the segment
+    const uint32_t rem = len > h0 ? len - h0 : 0u;
+    if (rem < (uint32_t)HALF)
+        m &= (1u << rem) - 1u;
+    return m;
+}
+
+template <int DM, bool VEC, bool NTL = true>
+__global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPlan P)
+{
+    __shared__ uint32_t slo[DM], shi[DM];
+    const int D = (int)P.D;
+    uint32_t lo[DM], hi[DM];
+#pragma unroll
+    for (int p = 0; p < DM; ++p) {
+        lo[p] = 0xFFFFFFFFu;
+        hi[p] = 0u;
+    }
+    for (int p = threadIdx.x; p < DM; p += NT) {
+        slo[p] = 0xFFFFFFFFu;
+        shi[p] = 0u;
+    }
+    const uint32_t lb = seg_logical_block();
+    const uint64_t g = gridDim.x;
+    for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
+        const uint64_t s = tile * NT + threadIdx.x;
+        if (s < P.nseg) {
+            const Seg sg = seg_of(P, s);
+            int64_t off[4];
+            seg_offsets<DM>(P, sg, off);
+            uint32_t m = seg_nonzero_half<VEC, NTL>(P, off, sg.len, 0);
+            if (sg.len > (uint32_t)HALF)
+                m |= seg_nonzero_half<VEC, NTL>(P, off, sg.len, HALF) << HALF;
+            if (m) {
+                double u[DM];
+                uint32_t tt[DM];
+                row_coords<DM>(P, sg.row, u, tt);
+                const uint32_t jmin = sg.j0 + (uint32_t)(__ffs(m) - 1);
+                const uint32_t jmax = sg.j0 + (uint32_t)(31 - __clz(m));
+                lo[0] = min(lo[0], jmin);
+                hi[0] = max(hi[0], jmax + 1u);
+#pragma unroll
+                for (int p = 1; p < DM; ++p) {
+                    if (p < D) {
+                        lo[p] = min(lo[p], tt[p]);
+                        hi[p] = max(hi[p], tt[p] + 1u);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < DM; ++p) {
+        if (p < D && hi[p]) {
+            atomicMin(&slo[p], lo[p]);
+            atomicMax(&shi[p], hi[p]);
+        }
+    }
+    __syncthreads();
+    // partials: 2*DM words per block, position-major (coalesced combine)
+    uint32_t *partials = (uint32_t *)((char *)(uintptr_t)P.ws + 256);
+    const uint32_t nb = P.nblocks;
+    for (int p = threadIdx.x; p < DM; p += NT) {
+        partials[(size_t)(2 * p) * nb + blockIdx.x] = slo[p];
+        partials[(size_t)(2 * p + 1) * nb + blockIdx.x] = shi[p];
+    }
+}
+
+// Combines the bbox partials and writes [lo_i, hi_i] per original axis
+// (int64; -1 everywhere when nothing qualifies; 0 on extent-1 axes).
+template <int DM>
+__global__ __launch_bounds__(NT) void bbox_final_kernel(const SegPlan P)
+{
+    __shared__ uint32_t flo[DM], fhi[DM];
+    __shared__ int pos_of[MAXD];
+    const int D = (int)P.D;
+    const uint32_t *partials = (const uint32_t *)((const char *)(uintptr_t)P.ws + 256);
+    const uint32_t nb = P.nblocks;
+    for (int p = threadIdx.x; p < DM; p += NT) {
+        flo[p] = 0xFFFFFFFFu;
+        fhi[p] = 0u;
+    }
+    if (threadIdx.x < MAXD)
+        pos_of[threadIdx.x] = -1;
+    __syncthreads();
+    // thread t folds blocks t, t + NT, .. for every position
+    for (int p = 0; p < D; ++p) {
+        uint32_t l = 0xFFFFFFFFu, h = 0u;
+        for (uint32_t b = threadIdx.x; b < nb; b += NT) {
+            l = min(l, partials[(size_t)(2 * p) * nb + b]);
+            h = max(h, partials[(size_t)(2 * p + 1) * nb + b]);
+        }
+        if (h) {
+            atomicMin(&flo[p], l);
+            atomicMax(&fhi[p], h);
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int p = 0; p < D; ++p) {
+            uint32_t o = P.orig[D - 1 - p];
+            if (o != 0xFFFFFFFFu)
+                pos_of[o] = p;
+        }
+    }
+    __syncthreads();
+    const bool found = fhi[0] != 0u;
+    int64_t *out = (int64_t *)(uintptr_t)P.out32;
+    const int d = (int)P.d_orig;
+    for (int i = threadIdx.x; i < d; i += NT) {
+        const int p = pos_of[i];
+        int64_t a = -1, b = -1;
+        if (found) {
+            a = (p < 0) ? 0 : (int64_t)flo[p];
+            b = (p < 0) ? 0 : (int64_t)fhi[p] - 1;
+        }
+        out[2 * i] = a;
+        out[2 * i + 1] = b;
+    }
+}
+
+// ---------------------------------------------------------------------
 
 template <int DM, bool COV>
 static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
 {
-    if (L.plan.vec4)
-        hipLaunchKernelGGL((moments_kernel<DM, COV, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
-    else
-        hipLaunchKernelGGL((moments_kernel<DM, COV, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+    const bool multi = L.plan.n > 1;
+    if (L.plan.vec4) {
+        if (multi)
+            hipLaunchKernelGGL((moments_kernel<DM, COV, true, true>), dim3(L.blocks), dim3(NT), 0, st,
+                               L.plan);
+        else
+            hipLaunchKernelGGL((moments_kernel<DM, COV, true, false>), dim3(L.blocks), dim3(NT), 0,
+                               st, L.plan);
+    } else {
+        if (multi)
+            hipLaunchKernelGGL((moments_kernel<DM, COV, false, true>), dim3(L.blocks), dim3(NT), 0,
+                               st, L.plan);
+        else
+            hipLaunchKernelGGL((moments_kernel<DM, COV, false, false>), dim3(L.blocks), dim3(NT), 0,
+                               st, L.plan);
+    }
     hipLaunchKernelGGL((moments_final_kernel<DM, COV>), dim3(1), dim3(FNT), 0, st, L.plan);
     return hipGetLastError();
 }
@@ -673,6 +927,52 @@ hipError_t launch_moments(const SegLaunch &L, hipStream_t st)
         }
     }
     return L.dm <= 8 ? go_moments<8, false>(L, st) : go_moments<32, false>(L, st);
+}
+
+template <int DM>
+static void go_dot(const SegLaunch &L, hipStream_t st)
+{
+    const bool multi = L.plan.n > 1;
+    if (L.plan.vec4) {
+        if (multi)
+            hipLaunchKernelGGL((dot_kernel<DM, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        else
+            hipLaunchKernelGGL((dot_kernel<DM, true, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+    } else {
+        if (multi)
+            hipLaunchKernelGGL((dot_kernel<DM, false, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        else
+            hipLaunchKernelGGL((dot_kernel<DM, false, false>), dim3(L.blocks), dim3(NT), 0, st,
+                               L.plan);
+    }
+}
+
+hipError_t launch_dot(const SegLaunch &L, hipStream_t st)
+{
+    if (L.dm <= 8)
+        go_dot<8>(L, st);
+    else
+        go_dot<32>(L, st);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(64), 0, st, L.plan);
+    return hipGetLastError();
+}
+
+hipError_t launch_bbox(const SegLaunch &L, hipStream_t st)
+{
+    if (L.dm <= 8) {
+        if (L.plan.vec4)
+            hipLaunchKernelGGL((bbox_kernel<8, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        else
+            hipLaunchKernelGGL((bbox_kernel<8, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        hipLaunchKernelGGL((bbox_final_kernel<8>), dim3(1), dim3(NT), 0, st, L.plan);
+    } else {
+        if (L.plan.vec4)
+            hipLaunchKernelGGL((bbox_kernel<32, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        else
+            hipLaunchKernelGGL((bbox_kernel<32, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        hipLaunchKernelGGL((bbox_final_kernel<32>), dim3(1), dim3(NT), 0, st, L.plan);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_moments_adj(const SegLaunch &L, hipStream_t st)
@@ -707,7 +1007,8 @@ template <int DM, bool COV> static int occ_moments(bool vec4)
     static int cache[2] = {0, 0};
     int &c = cache[vec4 ? 1 : 0];
     if (!c)
-        c = vec4 ? occupancy(moments_kernel<DM, COV, true>) : occupancy(moments_kernel<DM, COV, false>);
+        c = vec4 ? occupancy(moments_kernel<DM, COV, true, false>)
+                 : occupancy(moments_kernel<DM, COV, false, false>);
     return c;
 }
 

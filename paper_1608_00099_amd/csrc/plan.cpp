@@ -60,7 +60,8 @@ int device_cus()
 
 bool is_segment_op(triot_op op)
 {
-    return op == TRIOT_OP_MOMENTS || op == TRIOT_OP_MOMENTS_ADJ;
+    return op == TRIOT_OP_MOMENTS || op == TRIOT_OP_MOMENTS_ADJ || op == TRIOT_OP_DOT ||
+           op == TRIOT_OP_BBOX;
 }
 
 // Checked arithmetic on non-negative int64 values.
@@ -112,6 +113,8 @@ static bool is_output(triot_op op, int k)
     case TRIOT_OP_MUL_ACC:
     case TRIOT_OP_MUL:
     case TRIOT_OP_MOMENTS_ADJ:
+    case TRIOT_OP_XPYX_MZ:
+    case TRIOT_OP_CONV:
         return k == 0;
     case TRIOT_OP_MUL_ADJ:
         return k == 0 || k == 1;
@@ -124,15 +127,20 @@ triot_status validate(triot_op op, int n, int d, const int64_t *shapes, const in
                       void *const *tensors, const int64_t *bases, const void *params, Request *r)
 {
     std::memset(r, 0, sizeof(*r));
-    if ((int)op < 0 || (int)op > (int)TRIOT_OP_INDEX)
+    if ((int)op < 0 || (int)op > (int)TRIOT_OP_CONV)
         return TRIOT_E_INVALID;
     bool n_ok = false;
     switch (op) {
     case TRIOT_OP_COPY:
     case TRIOT_OP_EMBED_FILL: n_ok = (n == 2); break;
     case TRIOT_OP_MUL_ACC:
-    case TRIOT_OP_MUL: n_ok = (n == 3); break;
-    case TRIOT_OP_MOMENTS: n_ok = (n >= 1 && n <= 4); break;
+    case TRIOT_OP_MUL:
+    case TRIOT_OP_XPYX_MZ:
+    case TRIOT_OP_CONV: n_ok = (n == 3); break;
+    case TRIOT_OP_MOMENTS:
+    case TRIOT_OP_DOT:
+    case TRIOT_OP_MARGINAL:
+    case TRIOT_OP_BBOX: n_ok = (n >= 1 && n <= 4); break;
     case TRIOT_OP_MOMENTS_ADJ: n_ok = (n == 1); break;
     case TRIOT_OP_MUL_ADJ: n_ok = (n == 5); break;
     case TRIOT_OP_INDEX: n_ok = (n >= 1 && n <= MAXT); break;
@@ -169,6 +177,26 @@ triot_status validate(triot_op op, int n, int d, const int64_t *shapes, const in
         int f = ((const triot_moments_adj_params *)params)->flags;
         if (f & ~(TRIOT_MOMENTS_FIRST | TRIOT_MOMENTS_COV))
             return TRIOT_E_INVALID;
+    } else if (op == TRIOT_OP_MARGINAL) {
+        if (!params)
+            return TRIOT_E_INVALID;
+        uint32_t km = ((const triot_marginal_params *)params)->keep_mask;
+        if (d < 32 && (km >> d) != 0)
+            return TRIOT_E_INVALID;
+    } else if (op == TRIOT_OP_CONV) {
+        r->elem_bytes = 8;
+        if (bases)
+            for (int k = 0; k < n; ++k)
+                if (bases[k] != 0)
+                    return TRIOT_E_UNSUPPORTED;
+        // out = lhs + rhs - 1 on every axis, inputs non-empty
+        for (int i = 0; i < d; ++i) {
+            const int64_t so = shapes[i], sl = shapes[d + i], sr = shapes[2 * (size_t)d + i];
+            if (sl < 1 || sr < 1 || so != sl + sr - 1)
+                return TRIOT_E_BOUNDS;
+            if (counter && counter[i] != so)
+                return TRIOT_E_INVALID;
+        }
     }
 
     int64_t total[MAXT];
@@ -212,7 +240,8 @@ triot_status validate(triot_op op, int n, int d, const int64_t *shapes, const in
             c = counter[i];
             if (c < 0)
                 return TRIOT_E_INVALID;
-        } else if (op == TRIOT_OP_EMBED_FILL || op == TRIOT_OP_MOMENTS_ADJ) {
+        } else if (op == TRIOT_OP_EMBED_FILL || op == TRIOT_OP_MOMENTS_ADJ ||
+                   op == TRIOT_OP_CONV) {
             c = avail[0][i];
         } else if (op == TRIOT_OP_MUL_ADJ) {
             c = std::max(avail[0][i], avail[1][i]);
@@ -231,6 +260,23 @@ triot_status validate(triot_op op, int n, int d, const int64_t *shapes, const in
 
     int role[MAXT];
     roles(op, n, role);
+    if (op == TRIOT_OP_CONV) {
+        // The counter is the output shape; the inputs are read whole.
+        if (np == 0)
+            return TRIOT_OK;
+        for (int k = 0; k < n; ++k)
+            if (!tensors[k])
+                return TRIOT_E_INVALID;
+        uint64_t lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = (uint64_t)(uintptr_t)tensors[k];
+            hi[k] = lo[k] + (uint64_t)total[k] * 8;
+        }
+        for (int k = 1; k < 3; ++k)
+            if (lo[0] < hi[k] && lo[k] < hi[0])
+                return TRIOT_E_ALIAS;
+        return TRIOT_OK;
+    }
     for (int k = 0; k < n; ++k) {
         if (role[k] >= 0)
             continue;
@@ -265,7 +311,8 @@ triot_status validate(triot_op op, int n, int d, const int64_t *shapes, const in
     }
 
     // Aliasing: byte range touched by each operand over the counter.
-    if (op != TRIOT_OP_INDEX && op != TRIOT_OP_MOMENTS) {
+    if (op != TRIOT_OP_INDEX && op != TRIOT_OP_MOMENTS && op != TRIOT_OP_DOT &&
+        op != TRIOT_OP_MARGINAL && op != TRIOT_OP_BBOX) {
         uint64_t lo[MAXT], hi[MAXT];
         int64_t eb = (op == TRIOT_OP_COPY || op == TRIOT_OP_EMBED_FILL) ? r->elem_bytes : 4;
         for (int k = 0; k < n; ++k) {
@@ -758,12 +805,18 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     // dm(dm+1)/2 second sums, padded to a multiple of 8 (the final
     // reduction reads them 8 at a time, unconditionally).
     P.nterms = (uint32_t)((1 + dm + (cov ? dm * (dm + 1) / 2 : 0) + 7) / 8 * 8);
+    if (r.op == TRIOT_OP_DOT)
+        P.nterms = 8;                       // the mass alone
+    else if (r.op == TRIOT_OP_BBOX)
+        P.nterms = (uint32_t)(2 * dm);      // lo and hi + 1 per position (32-bit words)
 
     // Persistent grid: as many workgroups as can be resident at once (for
     // the moments pass at most 2 per CU: each workgroup ends in a reduction
     // of every term, and measured on MI355X, 2 per CU beat 4).
     const bool adj = r.op == TRIOT_OP_MOMENTS_ADJ;
-    int bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4);
+    int bpc = 2;   // the inner product and the bounding box: 2 per CU
+    if (r.op == TRIOT_OP_MOMENTS || adj)
+        bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4);
     if (!adj)
         bpc = std::min(bpc, 2);
     int64_t blocks = std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * bpc);
@@ -805,6 +858,120 @@ std::string sched_key(const Request &r)
         k += buf;
     }
     return k;
+}
+
+
+// ---------------------------------------------------------------------
+// Naive convolution plan
+// ---------------------------------------------------------------------
+triot_status plan_conv(const Request &r, ConvLaunch *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    ConvPlan &P = out->plan;
+    const int d = r.d;
+    P.d = (uint32_t)d;
+    uint64_t nout = 1, nl = 1, nr = 1;
+    for (int i = 0; i < d; ++i) {
+        const int64_t so = r.shape[0][i], sl = r.shape[1][i], sr = r.shape[2][i];
+        if (so >= (int64_t(1) << 32))
+            return TRIOT_E_UNSUPPORTED;
+        nout *= (uint64_t)so;
+        nl *= (uint64_t)sl;
+        nr *= (uint64_t)sr;
+        if (i >= 1) {
+            if (so >= 2)
+                magic_for((uint32_t)so, &P.ax[i]);
+            else
+                P.ax[i] = trivial_div();
+        }
+        P.ls[i] = (uint32_t)sl;
+        P.rs[i] = (uint32_t)sr;
+    }
+    if (nout >= (uint64_t(1) << 32))
+        return TRIOT_E_UNSUPPORTED;
+    for (int i = d - 1; i >= 0; --i) {
+        P.lstride[i] = (i == d - 1) ? 1 : P.lstride[i + 1] * (int64_t)P.ls[i + 1];
+        P.rstride[i] = (i == d - 1) ? 1 : P.rstride[i + 1] * (int64_t)P.rs[i + 1];
+    }
+    P.nout = nout;
+    P.nl = (uint32_t)std::min<uint64_t>(nl, 0xFFFFFFFFu);
+    P.nr = (uint32_t)std::min<uint64_t>(nr, 0xFFFFFFFFu);
+    P.lds = (nl + nr <= conv_lds_words()) ? 1u : 0u;
+    P.out = (uint64_t)(uintptr_t)r.ptr[0];
+    P.lhs = (uint64_t)(uintptr_t)r.ptr[1];
+    P.rhs = (uint64_t)(uintptr_t)r.ptr[2];
+    return TRIOT_OK;
+}
+
+// ---------------------------------------------------------------------
+// Marginalization plan
+// ---------------------------------------------------------------------
+// Threads aimed at per launch: the reduced sub-box of each kept tuple is
+// split into parts until about this many threads run.
+static int64_t marginal_thread_target(int cus) { return (int64_t)cus * 1024; }
+
+size_t marginal_workspace_bytes(int cus)
+{
+    // parts > 1 only when nout < target, and then nout * parts < 2 * target
+    return 256 + (size_t)(2 * marginal_thread_target(cus)) * sizeof(double);
+}
+
+triot_status plan_marginal(const Request &r, int cus, MargLaunch *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    MargPlan &P = out->plan;
+    const int n = r.n, d = r.d;
+    const uint32_t km = ((const triot_marginal_params *)r.params)->keep_mask;
+    int dk = 0, dr = 0;
+    uint64_t nout = 1, nred = 1;
+    for (int i = 0; i < d; ++i) {
+        const int64_t c = r.counter[i];
+        if (c == 1)
+            continue;             // contributes nothing to any offset or index
+        if (c >= (int64_t(1) << 32))
+            return TRIOT_E_UNSUPPORTED;
+        int64_t st[MAXT];
+        for (int k = 0; k < n; ++k) {
+            int64_t v = 1;
+            for (int j = i + 1; j < d; ++j)
+                v *= r.shape[k][j];
+            st[k] = v;
+        }
+        if ((km >> i) & 1u) {
+            magic_for((uint32_t)c, &P.kax[dk]);
+            for (int k = 0; k < n; ++k)
+                P.kstride[k][dk] = st[k];
+            nout *= (uint64_t)c;
+            ++dk;
+        } else {
+            magic_for((uint32_t)c, &P.rax[dr]);
+            for (int k = 0; k < n; ++k)
+                P.rstride[k][dr] = st[k];
+            nred *= (uint64_t)c;
+            ++dr;
+        }
+    }
+    if (nout >= (uint64_t(1) << 32))
+        return TRIOT_E_UNSUPPORTED;
+    const int64_t target = marginal_thread_target(cus);
+    uint64_t parts = 1;
+    if ((int64_t)nout < target) {
+        parts = (uint64_t)((target + (int64_t)nout - 1) / (int64_t)nout);
+        // at least 64 reduced tuples per part
+        parts = std::min<uint64_t>(parts, std::max<uint64_t>(1, nred / 64));
+    }
+    P.n = (uint32_t)n;
+    P.dk = (uint32_t)dk;
+    P.dr = (uint32_t)dr;
+    P.parts = (uint32_t)parts;
+    P.nout = nout;
+    P.nred = nred;
+    for (int k = 0; k < n; ++k) {
+        P.base[k] = r.base[k];
+        P.ptr[k] = (uint64_t)(uintptr_t)r.ptr[k];
+    }
+    (void)cus;
+    return TRIOT_OK;
 }
 
 }  // namespace triot

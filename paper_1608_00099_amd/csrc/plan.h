@@ -55,6 +55,14 @@ struct SegLaunch {
     int dmax;       // register tier of the adjoint (8 or 32)
 };
 
+struct ConvLaunch {
+    ConvPlan plan;
+};
+
+struct MargLaunch {
+    MargPlan plan;
+};
+
 // Number of compute units of the current device (cached per device).
 int device_cus();
 
@@ -67,6 +75,10 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
 triot_status plan_segment(const Request &r, int cus, SegLaunch *out);
 
 size_t segment_workspace_bytes(const SegLaunch &l);
+
+triot_status plan_conv(const Request &r, ConvLaunch *out);
+triot_status plan_marginal(const Request &r, int cus, MargLaunch *out);
+size_t marginal_workspace_bytes(int cus);
 
 // Key of the schedule cache: everything the plan shape depends on.
 std::string sched_key(const Request &r);

@@ -27,7 +27,7 @@ def kernel_source_hash():
     """Hash of the kernel and planner sources (a traffic record is valid
     only for the sources it was measured on)."""
     h = hashlib.sha256()
-    for f in ("common.h", "kern_coiter.hip", "kern_segment.hip", "plan.cpp"):
+    for f in ("common.h", "kern_coiter.hip", "kern_segment.hip", "kern_reduce.hip", "plan.cpp"):
         with open(os.path.join(ROOT, "paper_1608_00099_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
