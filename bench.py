@@ -227,7 +227,7 @@ def graph_ms(fn, reps=10):
     return t
 
 
-EXTRAS = ("ceiling", "cfg1", "cfg3", "cfg4", "cfg5")
+EXTRAS = ("ceiling", "cfg1", "cfg3", "cfg4", "cfg5", "paper", "reduce", "fftconv")
 
 
 def extras(dev, only=None):
@@ -254,7 +254,101 @@ def extras(dev, only=None):
         _cfg4(dev, out)
     if want("cfg5"):
         _cfg5(dev, out)
+    if want("paper"):
+        _paper(dev, flush, out)
+    if want("reduce"):
+        _reduce(dev, flush, out)
+    if want("fftconv"):
+        _fftconv(dev, out)
     return out
+
+
+def _cold_warm(fn, flush, nbytes):
+    """Median GPU time of fn after a 1 GiB write (cold) and right after
+    itself (warm), with the effective GB/s of nbytes."""
+    c = event_ms(fn, pre=lambda: flush.fill_(0.0))
+    w = event_ms(fn)
+    return {"cold": dict(c, GBs=nbytes / c["median_ms"] / 1e6),
+            "warm": dict(w, GBs=nbytes / w["median_ms"] / 1e6), "bytes": nbytes}
+
+
+def _paper(dev, flush, out):
+    """The paper's four benchmarks (Section 3) at its shapes."""
+    import torch
+    from paper_1608_00099_amd import api
+    big, small = (1 << 10, 1 << 9, 1 << 8), (1 << 9, 1 << 9, 1 << 5)
+    # benchmark 1: crop (2^10, 2^9, 2^8) -> (2^9, 2^9, 2^5), float32 and float64
+    for dt, name in ((torch.float32, "f32"), (torch.float64, "f64")):
+        a = torch.rand(big, dtype=dt, device=dev)
+        o = torch.empty(small, dtype=dt, device=dev)
+        nb = 2 * prod(small) * a.element_size()
+        out["paper_b1_crop_" + name] = _cold_warm(lambda: api.copy_(o, a, counter=small), flush, nb)
+        del a, o
+    # benchmark 2: inner product over the shared tuples
+    a = torch.rand(big, dtype=torch.float32, device=dev)
+    b = torch.rand(small, dtype=torch.float32, device=dev)
+    out["paper_b2_dot"] = _cold_warm(lambda: api.dot(a, b), flush, 8 * prod(small))
+    del a, b
+    # benchmark 3: x <- x + y*x - z at the paper's shapes
+    xs, ys, zs = (129, 32, 13, 16), (253, 64, 64, 23), (256, 39, 64, 33)
+    x = torch.rand(xs, device=dev)
+    y = torch.rand(ys, device=dev)
+    z = torch.rand(zs, device=dev)
+    out["paper_b3_update"] = _cold_warm(lambda: api.xpyx_mz_(x, y, z), flush, 16 * prod(xs))
+    del x, y, z
+    # benchmark 4: naive convolution of two (2^8, 2^3) float64 matrices
+    l = torch.rand((256, 8), dtype=torch.float64, device=dev)
+    r = torch.rand((256, 8), dtype=torch.float64, device=dev)
+    o = torch.empty((511, 15), dtype=torch.float64, device=dev)
+    t = event_ms(lambda: api.conv(l, r, out=o), reps=20)
+    macs = prod((256, 8)) * prod((256, 8))
+    out["paper_b4_conv"] = dict(t, multiply_adds=macs,
+                                GFLOPs=2 * macs / t["median_ms"] / 1e6)
+    log("paper benchmarks done")
+
+
+def _reduce(dev, flush, out):
+    """Marginalization and the nonzero bounding box over the 16^6 PMF."""
+    import torch
+    from paper_1608_00099_amd import api, inputs
+    p = torch.from_numpy(inputs.cfg3_values()).to(dev)
+    nb = 4 * p.numel()
+    out["marginal_16pow6_keep0"] = _cold_warm(lambda: api.marginal(p, (1, 0, 0, 0, 0, 0)), flush,
+                                              nb)
+    out["marginal_16pow6_keep5"] = _cold_warm(lambda: api.marginal(p, (1, 1, 1, 1, 1, 0)), flush,
+                                              nb)
+    sparse = torch.where(torch.rand_like(p) < 1e-3, p, torch.zeros_like(p))
+    out["bbox_16pow6"] = _cold_warm(lambda: api.bbox(sparse), flush, nb)
+    out["dot_16pow6_2ops"] = _cold_warm(lambda: api.dot(p, sparse), flush, 2 * nb)
+    log("reductions done")
+
+
+def _fftconv(dev, out):
+    """FFT convolution of a batch of 3-d pairs: the share of the zero-pads and
+    the crop (this library's kernels) against the transforms."""
+    import torch
+    from paper_1608_00099_amd import api, fftconv
+    B, sx, sy = 64, (48, 48, 48), (16, 16, 16)
+    x = torch.rand((B,) + sx, device=dev)
+    y = torch.rand((B,) + sy, device=dev)
+    s = fftconv.conv_shape(sx, sy)
+    n = tuple(fftconv.good_size(v) for v in s)
+    fftconv.fft_conv(x, y, batch_dims=1)          # plans the transforms
+    t_all = event_ms(lambda: fftconv.fft_conv(x, y, batch_dims=1), reps=10)
+    xp = api.pad_embed(x, (B,) + n)
+    yp = api.pad_embed(y, (B,) + n)
+    full = torch.empty((B,) + n, device=dev)
+    t_pad = event_ms(lambda: (api.pad_embed(x, (B,) + n), api.pad_embed(y, (B,) + n)), reps=10)
+    t_crop = event_ms(lambda: api.crop(full, (B,) + s), reps=10)
+    pad_bytes = 4 * B * (prod(sx) + prod(sy) + 2 * prod(n))
+    crop_bytes = 8 * B * prod(s)
+    out["fftconv_b64_48c_16c"] = {
+        "total": t_all, "pads": dict(t_pad, GBs=pad_bytes / t_pad["median_ms"] / 1e6),
+        "crop": dict(t_crop, GBs=crop_bytes / t_crop["median_ms"] / 1e6),
+        "pad_crop_share": (t_pad["median_ms"] + t_crop["median_ms"]) / t_all["median_ms"],
+        "fft_shape": list(n)}
+    del xp, yp, full
+    log("fft convolution done")
 
 
 def _cfg1(dev, out):

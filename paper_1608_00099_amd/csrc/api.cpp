@@ -304,8 +304,8 @@ extern "C" triot_status triot_plan_describe(triot_op op, int n_tensors, int d, c
             info->extents[i] = r.shape[0][i];
         info->vec = L.plan.lds ? 1 : 0;       // 1: inputs staged in LDS
         info->units = (int64_t)L.plan.nout;
-        info->blocks = (int)((L.plan.nout + 255) / 256);
-        info->threads = 256;
+        info->blocks = (int)((L.plan.nout + 63) / 64);
+        info->threads = 64;
         info->unroll = 1;
         return TRIOT_OK;
     }

@@ -20,6 +20,8 @@
 // parts a second kernel adds them in order.  Deterministic.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -33,8 +35,29 @@ __device__ __forceinline__ uint32_t rdiv_u32(uint32_t n, const AxisDiv &a)
     return (h + ((n - h) >> 1)) >> a.s;
 }
 
-constexpr int CONV_NT = 256;
+constexpr int CONV_NT = 64;   // one wave per workgroup: outputs spread over more CUs
 constexpr uint32_t CONV_LDS_WORDS = 8192;   // float64 words of LDS staging (64 KiB)
+
+// Copies n float64 words from global memory to LDS with 16 loads in flight
+// per thread (one round trip per 16 * CONV_NT words, not per CONV_NT).
+__device__ __forceinline__ void stage_lds(double *dst, const GLOBAL double *src, uint32_t n)
+{
+    constexpr int K = 16;
+    for (uint32_t b = threadIdx.x; b < n; b += K * CONV_NT) {
+        double tmp[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const uint32_t i = b + (uint32_t)u * CONV_NT;
+            tmp[u] = src[i < n ? i : 0u];
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const uint32_t i = b + (uint32_t)u * CONV_NT;
+            if (i < n)
+                dst[i] = tmp[u];
+        }
+    }
+}
 
 template <bool LDS>
 __global__ __launch_bounds__(CONV_NT) void conv_kernel(const ConvPlan P)
@@ -43,10 +66,8 @@ __global__ __launch_bounds__(CONV_NT) void conv_kernel(const ConvPlan P)
     const GLOBAL double *gl = (const GLOBAL double *)(uintptr_t)P.lhs;
     const GLOBAL double *gr = (const GLOBAL double *)(uintptr_t)P.rhs;
     if (LDS) {
-        for (uint32_t i = threadIdx.x; i < P.nl; i += CONV_NT)
-            sm[i] = gl[i];
-        for (uint32_t i = threadIdx.x; i < P.nr; i += CONV_NT)
-            sm[P.nl + i] = gr[i];
+        stage_lds(sm, gl, P.nl);
+        stage_lds(sm + P.nl, gr, P.nr);
         __syncthreads();
     }
     const double *L = LDS ? sm : (const double *)gl;
@@ -84,16 +105,27 @@ __global__ __launch_bounds__(CONV_NT) void conv_kernel(const ConvPlan P)
         acc = acc + L[0] * R[0];
     } else {
         const int in = d - 1;
-        const int64_t ls_in = P.lstride[in], rs_in = P.rstride[in];
         const uint32_t nin = hi[in] - lo[in] + 1;
         while (true) {
-            // innermost axis: lhs index up by one, rhs index down by one
-            int64_t li = lrow, ri = rrow;
-            for (uint32_t k = 0; k < nin; ++k) {
-                const double prod = L[li] * R[ri];
+            // innermost axis (unit stride in both inputs): lhs index up by
+            // one, rhs index down by one; loads run ahead of the sequential
+            // additions, which keep the paper's order
+            const double *lp = L + lrow;
+            const double *rp = R + rrow;
+            uint32_t k = 0;
+            for (; k + 4 <= nin; k += 4) {
+                const double a0 = lp[k], a1 = lp[k + 1], a2 = lp[k + 2], a3 = lp[k + 3];
+                const double b0 = rp[-(int64_t)k], b1 = rp[-(int64_t)k - 1];
+                const double b2 = rp[-(int64_t)k - 2], b3 = rp[-(int64_t)k - 3];
+                const double p0 = a0 * b0, p1 = a1 * b1, p2 = a2 * b2, p3 = a3 * b3;
+                acc = acc + p0;
+                acc = acc + p1;
+                acc = acc + p2;
+                acc = acc + p3;
+            }
+            for (; k < nin; ++k) {
+                const double prod = lp[k] * rp[-(int64_t)k];
                 acc = acc + prod;
-                li += ls_in;
-                ri -= rs_in;
             }
             // next tuple of the outer axes (carry), else done
             int i = in - 1;
@@ -115,25 +147,199 @@ __global__ __launch_bounds__(CONV_NT) void conv_kernel(const ConvPlan P)
     ((GLOBAL double *)(uintptr_t)P.out)[f] = acc;
 }
 
+// The same gather for a dimension D known at compile time (1..4): the
+// per-axis state lives in registers, and the valid box is walked as one
+// flattened loop in lexicographic order.  DEPTH steps of index arithmetic
+// and their loads run ahead of the DEPTH additions, which stay in order
+// (few waves share a CU here, so the loads' latency must overlap within
+// the thread).  IDX: 32-bit indices when the inputs sit in LDS.
+template <int D, bool LDS>
+__global__ __launch_bounds__(CONV_NT) void conv_kernel_d(const ConvPlan P)
+{
+    typedef typename std::conditional<LDS, int32_t, int64_t>::type IDX;
+    constexpr int DEPTH = 16;
+    extern __shared__ double sm[];
+    const GLOBAL double *gl = (const GLOBAL double *)(uintptr_t)P.lhs;
+    const GLOBAL double *gr = (const GLOBAL double *)(uintptr_t)P.rhs;
+    if (LDS) {
+        stage_lds(sm, gl, P.nl);
+        stage_lds(sm + P.nl, gr, P.nr);
+        __syncthreads();
+    }
+    const double *L = LDS ? sm : (const double *)gl;
+    const double *R = LDS ? sm + P.nl : (const double *)gr;
+    const uint64_t f = (uint64_t)blockIdx.x * CONV_NT + threadIdx.x;
+    if (f >= P.nout)
+        return;
+    uint32_t v[D];
+    uint32_t q = (uint32_t)f;
+#pragma unroll
+    for (int i = D - 1; i >= 1; --i) {
+        if (P.ax[i].c == 1) {
+            v[i] = 0;
+        } else {
+            const uint32_t qq = rdiv_u32(q, P.ax[i]);
+            v[i] = q - qq * P.ax[i].c;
+            q = qq;
+        }
+    }
+    v[0] = q;
+    uint32_t nbox[D], c[D];
+    IDX li = 0, ri = 0, lst[D], rst[D];
+    uint32_t total = 1;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const uint32_t lo = v[i] + 1 > P.rs[i] ? v[i] + 1 - P.rs[i] : 0u;
+        const uint32_t hi = min(v[i], P.ls[i] - 1);
+        nbox[i] = hi - lo + 1;
+        total *= nbox[i];
+        c[i] = 0;
+        lst[i] = (IDX)P.lstride[i];
+        rst[i] = (IDX)P.rstride[i];
+        li += (IDX)lo * lst[i];
+        ri += (IDX)(v[i] - lo) * rst[i];
+    }
+    // advance (li, ri) to the next tuple of the box, lexicographically
+    auto step = [&]() {
+#pragma unroll
+        for (int i = D - 1; i >= 0; --i) {
+            ++c[i];
+            li += lst[i];
+            ri -= rst[i];
+            if (i == 0 || c[i] < nbox[i])
+                break;
+            li -= (IDX)nbox[i] * lst[i];
+            ri += (IDX)nbox[i] * rst[i];
+            c[i] = 0;
+        }
+    };
+    double acc = 0.0;
+    for (uint32_t s0 = 0; s0 < total; s0 += DEPTH) {
+        double a[DEPTH], b[DEPTH];
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            const bool ok = s0 + (uint32_t)u < total;
+            a[u] = L[ok ? li : 0];
+            b[u] = R[ok ? ri : 0];
+            if (s0 + (uint32_t)u + 1 < total)
+                step();
+        }
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            if (s0 + (uint32_t)u < total) {
+                const double prod = a[u] * b[u];
+                acc = acc + prod;
+            }
+        }
+    }
+    ((GLOBAL double *)(uintptr_t)P.out)[f] = acc;
+}
+
+// Dimensions 1 and 2 (benchmark 4 is 2-d): the box is walked as nested
+// loops, rows of the lhs box outside, inside them chunks of 8 terms read at
+// fixed offsets from one row pointer (no per-term index arithmetic or
+// carry).  The inputs sit in LDS between 8 words of padding on each side,
+// so the chunk's reads past a row's end stay inside the allocation; those
+// terms are never added.  The additions keep the paper's order.
+constexpr uint32_t CONV_PAD = 8;
+
+template <int D>
+__global__ __launch_bounds__(CONV_NT) void conv_kernel_rows(const ConvPlan P)
+{
+    extern __shared__ double sm[];
+    double *Ls = sm + CONV_PAD;
+    double *Rs = sm + CONV_PAD + P.nl + CONV_PAD;
+    stage_lds(Ls, (const GLOBAL double *)(uintptr_t)P.lhs, P.nl);
+    stage_lds(Rs, (const GLOBAL double *)(uintptr_t)P.rhs, P.nr);
+    __syncthreads();
+    const uint64_t f = (uint64_t)blockIdx.x * CONV_NT + threadIdx.x;
+    if (f >= P.nout)
+        return;
+    // output tuple (v0, v1); for D == 1 the outer axis is a single row
+    uint32_t v0 = 0, v1;
+    if (D == 2) {
+        if (P.ax[1].c == 1) {
+            v1 = 0;
+            v0 = (uint32_t)f;
+        } else {
+            v0 = rdiv_u32((uint32_t)f, P.ax[1]);
+            v1 = (uint32_t)f - v0 * P.ax[1].c;
+        }
+    } else {
+        v1 = (uint32_t)f;
+    }
+    const uint32_t ls0 = D == 2 ? P.ls[0] : 1u, rs0 = D == 2 ? P.rs[0] : 1u;
+    const uint32_t ls1 = P.ls[D - 1], rs1 = P.rs[D - 1];
+    const uint32_t lo0 = v0 + 1 > rs0 ? v0 + 1 - rs0 : 0u, hi0 = min(v0, ls0 - 1);
+    const uint32_t lo1 = v1 + 1 > rs1 ? v1 + 1 - rs1 : 0u, hi1 = min(v1, ls1 - 1);
+    const uint32_t n0 = hi0 - lo0 + 1, n1 = hi1 - lo1 + 1;
+    int32_t lrow = (int32_t)(lo0 * ls1 + lo1);
+    int32_t rrow = (int32_t)((v0 - lo0) * rs1 + (v1 - lo1));
+    double acc = 0.0;
+    for (uint32_t j = 0; j < n0; ++j) {
+        const double *lp = Ls + lrow;
+        const double *rp = Rs + rrow;
+        for (uint32_t k0 = 0; k0 < n1; k0 += 8) {
+            double a[8], b[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                a[u] = lp[k0 + u];
+                b[u] = rp[-(int32_t)k0 - u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (k0 + (uint32_t)u < n1) {
+                    const double prod = a[u] * b[u];
+                    acc = acc + prod;
+                }
+            }
+        }
+        lrow += (int32_t)ls1;
+        rrow -= (int32_t)rs1;
+    }
+    ((GLOBAL double *)(uintptr_t)P.out)[f] = acc;
+}
+
+template <bool LDS>
+static void go_conv(const ConvLaunch &L, uint32_t blocks, size_t bytes, hipStream_t st)
+{
+    switch (L.plan.d) {
+    case 1: hipLaunchKernelGGL((conv_kernel_d<1, LDS>), dim3(blocks), dim3(CONV_NT), bytes, st, L.plan); break;
+    case 2: hipLaunchKernelGGL((conv_kernel_d<2, LDS>), dim3(blocks), dim3(CONV_NT), bytes, st, L.plan); break;
+    case 3: hipLaunchKernelGGL((conv_kernel_d<3, LDS>), dim3(blocks), dim3(CONV_NT), bytes, st, L.plan); break;
+    case 4: hipLaunchKernelGGL((conv_kernel_d<4, LDS>), dim3(blocks), dim3(CONV_NT), bytes, st, L.plan); break;
+    default: hipLaunchKernelGGL((conv_kernel<LDS>), dim3(blocks), dim3(CONV_NT), bytes, st, L.plan); break;
+    }
+}
+
 hipError_t launch_conv(const ConvLaunch &L, hipStream_t st)
 {
     const uint32_t blocks = (uint32_t)((L.plan.nout + CONV_NT - 1) / CONV_NT);
-    if (L.plan.lds) {
-        const size_t bytes = (size_t)(L.plan.nl + L.plan.nr) * sizeof(double);
-        hipLaunchKernelGGL((conv_kernel<true>), dim3(blocks), dim3(CONV_NT), bytes, st, L.plan);
-    } else {
-        hipLaunchKernelGGL((conv_kernel<false>), dim3(blocks), dim3(CONV_NT), 0, st, L.plan);
+    if (L.plan.lds && (L.plan.d == 1 || L.plan.d == 2)) {
+        const size_t bytes = (size_t)(L.plan.nl + L.plan.nr + 3 * CONV_PAD) * sizeof(double);
+        if (L.plan.d == 1)
+            hipLaunchKernelGGL((conv_kernel_rows<1>), dim3(blocks), dim3(CONV_NT), bytes, st, L.plan);
+        else
+            hipLaunchKernelGGL((conv_kernel_rows<2>), dim3(blocks), dim3(CONV_NT), bytes, st, L.plan);
+        return hipGetLastError();
     }
+    if (L.plan.lds)
+        go_conv<true>(L, blocks, (size_t)(L.plan.nl + L.plan.nr) * sizeof(double), st);
+    else
+        go_conv<false>(L, blocks, 0, st);
     return hipGetLastError();
 }
 
-uint32_t conv_lds_words() { return CONV_LDS_WORDS; }
+uint32_t conv_lds_words() { return CONV_LDS_WORDS - 3 * 8; }
 
 // ---------------------------------------------------------------------
 // Marginalization
 // ---------------------------------------------------------------------
 constexpr int MARG_NT = 256;
 
+// RD > 0: exactly RD reduced axes, known at compile time (the odometer in
+// registers); RD == 0: any number.
+template <int RD>
 __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
 {
     const uint64_t gid = (uint64_t)blockIdx.x * MARG_NT + threadIdx.x;
@@ -142,7 +348,8 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
         return;
     const uint32_t o = (uint32_t)(gid % P.nout);
     const uint32_t p = (uint32_t)(gid / P.nout);
-    const int n = (int)P.n, dk = (int)P.dk, dr = (int)P.dr;
+    const int n = (int)P.n, dk = (int)P.dk, dr = RD > 0 ? RD : (int)P.dr;
+    constexpr int TN = RD > 0 ? RD : MAXD;
     int64_t off[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -168,9 +375,10 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
     // part p of the reduced sub-box: flat range [r0, r1)
     const uint64_t r0 = (uint64_t)p * P.nred / P.parts;
     const uint64_t r1 = (uint64_t)(p + 1) * P.nred / P.parts;
-    uint32_t t[MAXD];
+    uint32_t t[TN];
     {
         uint64_t q = r0;
+#pragma unroll
         for (int i = dr - 1; i >= 0; --i) {
             const uint64_t c = P.rax[i].c;
             const uint64_t digit = (i == 0) ? q : q % c;
@@ -191,6 +399,7 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
                 w *= (double)((const GLOBAL float *)(uintptr_t)P.ptr[k])[off[k]];
         acc += w;
         // advance the odometer over the reduced axes
+#pragma unroll
         for (int i = dr - 1; i >= 0; --i) {
             if (++t[i] < P.rax[i].c || i == 0) {
 #pragma unroll
@@ -215,27 +424,44 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
     }
 }
 
+// One wave per output: lane l adds parts l, l + 64, .. (loads in flight
+// together), then the wave folds its 64 sums by a butterfly.  Fixed order.
 __global__ __launch_bounds__(MARG_NT) void marginal_final_kernel(const MargPlan P)
 {
-    const uint64_t o = (uint64_t)blockIdx.x * MARG_NT + threadIdx.x;
-    if (o >= P.nout)
-        return;
-    const double *part = (const double *)((const char *)(uintptr_t)P.ws + 256) + o * P.parts;
+    const uint64_t o = (uint64_t)blockIdx.x * (MARG_NT / 64) + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
     double acc = 0.0;
-    for (uint32_t p = 0; p < P.parts; ++p)
-        acc += part[p];
-    ((float *)(uintptr_t)P.out32)[o] = (float)acc;
-    if (P.out64)
-        ((double *)(uintptr_t)P.out64)[o] = acc;
+    if (o < P.nout) {
+        const GLOBAL double *part =
+            (const GLOBAL double *)((uintptr_t)P.ws + 256) + o * P.parts;
+        for (uint32_t p = lane; p < P.parts; p += 64)
+            acc += part[p];
+    }
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1)
+        acc += __shfl_xor(acc, k, 64);
+    if (o < P.nout && lane == 0) {
+        ((float *)(uintptr_t)P.out32)[o] = (float)acc;
+        if (P.out64)
+            ((double *)(uintptr_t)P.out64)[o] = acc;
+    }
 }
 
 hipError_t launch_marginal(const MargLaunch &L, hipStream_t st)
 {
     const uint64_t total = L.plan.nout * L.plan.parts;
     const uint32_t blocks = (uint32_t)((total + MARG_NT - 1) / MARG_NT);
-    hipLaunchKernelGGL(marginal_kernel, dim3(blocks), dim3(MARG_NT), 0, st, L.plan);
+    switch (L.plan.dr) {
+    case 1: hipLaunchKernelGGL((marginal_kernel<1>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 2: hipLaunchKernelGGL((marginal_kernel<2>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 3: hipLaunchKernelGGL((marginal_kernel<3>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 4: hipLaunchKernelGGL((marginal_kernel<4>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 5: hipLaunchKernelGGL((marginal_kernel<5>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 6: hipLaunchKernelGGL((marginal_kernel<6>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    default: hipLaunchKernelGGL((marginal_kernel<0>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    }
     if (L.plan.parts > 1) {
-        const uint32_t fb = (uint32_t)((L.plan.nout + MARG_NT - 1) / MARG_NT);
+        const uint32_t fb = (uint32_t)((L.plan.nout + MARG_NT / 64 - 1) / (MARG_NT / 64));
         hipLaunchKernelGGL(marginal_final_kernel, dim3(fb), dim3(MARG_NT), 0, st, L.plan);
     }
     return hipGetLastError();

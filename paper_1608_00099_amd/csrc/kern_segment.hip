@@ -687,22 +687,30 @@ __global__ __launch_bounds__(NT, 4) void dot_kernel(const SegPlan P)
         ((double *)((char *)(uintptr_t)P.ws + 256))[blockIdx.x] = tot[0];
 }
 
-// Sum of the per-workgroup partials (32 lanes, fixed order), written as
-// float32 to out32[0] and, when requested, float64 to out64[0].
-__global__ __launch_bounds__(64) void dot_final_kernel(const SegPlan P)
+// Sum of the per-workgroup partials, written as float32 to out32[0] and,
+// when requested, float64 to out64[0].  One workgroup of FNT threads:
+// thread t loads partials t, t + FNT, .. (all loads of a pass in flight
+// together), then the workgroup folds in a fixed tree (half-wave shuffles,
+// then the half waves' sums in order).
+__global__ __launch_bounds__(FNT) void dot_final_kernel(const SegPlan P)
 {
+    __shared__ double hw[FNT / 32];
     const GLOBAL double *partials = (const GLOBAL double *)((uintptr_t)P.ws + 256);
     const uint32_t nb = P.nblocks;
-    const int lane = threadIdx.x & 31;
     double v = 0.0;
-    if (threadIdx.x < 32)
-        for (uint32_t b = lane; b < nb; b += 32)
-            v += partials[b];
+    for (uint32_t b = threadIdx.x; b < nb; b += FNT)
+        v += partials[b];
     v = half_wave_sum(v);
+    if ((threadIdx.x & 31) == 0)
+        hw[threadIdx.x >> 5] = v;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        ((float *)(uintptr_t)P.out32)[0] = (float)v;
+        double t = 0.0;
+        for (int i = 0; i < FNT / 32; ++i)
+            t += hw[i];
+        ((float *)(uintptr_t)P.out32)[0] = (float)t;
         if (P.out64)
-            ((double *)(uintptr_t)P.out64)[0] = v;
+            ((double *)(uintptr_t)P.out64)[0] = t;
     }
 }
 
@@ -834,32 +842,40 @@ __global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPl
 }
 
 // Combines the bbox partials and writes [lo_i, hi_i] per original axis
-// (int64; -1 everywhere when nothing qualifies; 0 on extent-1 axes).
+// (int64; -1 everywhere when nothing qualifies; 0 on extent-1 axes).  One
+// workgroup of FNT threads: thread t loads block t's 2 * D words at once
+// (one round trip), then folds them into LDS with min / max atomics, which
+// do not depend on order.
 template <int DM>
-__global__ __launch_bounds__(NT) void bbox_final_kernel(const SegPlan P)
+__global__ __launch_bounds__(FNT) void bbox_final_kernel(const SegPlan P)
 {
     __shared__ uint32_t flo[DM], fhi[DM];
     __shared__ int pos_of[MAXD];
     const int D = (int)P.D;
-    const uint32_t *partials = (const uint32_t *)((const char *)(uintptr_t)P.ws + 256);
+    const GLOBAL uint32_t *partials = (const GLOBAL uint32_t *)((uintptr_t)P.ws + 256);
     const uint32_t nb = P.nblocks;
-    for (int p = threadIdx.x; p < DM; p += NT) {
+    for (int p = threadIdx.x; p < DM; p += FNT) {
         flo[p] = 0xFFFFFFFFu;
         fhi[p] = 0u;
     }
     if (threadIdx.x < MAXD)
         pos_of[threadIdx.x] = -1;
     __syncthreads();
-    // thread t folds blocks t, t + NT, .. for every position
-    for (int p = 0; p < D; ++p) {
-        uint32_t l = 0xFFFFFFFFu, h = 0u;
-        for (uint32_t b = threadIdx.x; b < nb; b += NT) {
-            l = min(l, partials[(size_t)(2 * p) * nb + b]);
-            h = max(h, partials[(size_t)(2 * p + 1) * nb + b]);
+    for (uint32_t b = threadIdx.x; b < nb; b += FNT) {
+        uint32_t l[DM], h[DM];
+#pragma unroll
+        for (int p = 0; p < DM; ++p) {
+            if (p < D) {
+                l[p] = partials[(size_t)(2 * p) * nb + b];
+                h[p] = partials[(size_t)(2 * p + 1) * nb + b];
+            }
         }
-        if (h) {
-            atomicMin(&flo[p], l);
-            atomicMax(&fhi[p], h);
+#pragma unroll
+        for (int p = 0; p < DM; ++p) {
+            if (p < D && h[p]) {
+                atomicMin(&flo[p], l[p]);
+                atomicMax(&fhi[p], h[p]);
+            }
         }
     }
     if (threadIdx.x == 0) {
@@ -873,7 +889,7 @@ __global__ __launch_bounds__(NT) void bbox_final_kernel(const SegPlan P)
     const bool found = fhi[0] != 0u;
     int64_t *out = (int64_t *)(uintptr_t)P.out32;
     const int d = (int)P.d_orig;
-    for (int i = threadIdx.x; i < d; i += NT) {
+    for (int i = threadIdx.x; i < d; i += FNT) {
         const int p = pos_of[i];
         int64_t a = -1, b = -1;
         if (found) {
@@ -953,7 +969,7 @@ hipError_t launch_dot(const SegLaunch &L, hipStream_t st)
         go_dot<8>(L, st);
     else
         go_dot<32>(L, st);
-    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(64), 0, st, L.plan);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(FNT), 0, st, L.plan);
     return hipGetLastError();
 }
 
@@ -964,13 +980,13 @@ hipError_t launch_bbox(const SegLaunch &L, hipStream_t st)
             hipLaunchKernelGGL((bbox_kernel<8, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
         else
             hipLaunchKernelGGL((bbox_kernel<8, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
-        hipLaunchKernelGGL((bbox_final_kernel<8>), dim3(1), dim3(NT), 0, st, L.plan);
+        hipLaunchKernelGGL((bbox_final_kernel<8>), dim3(1), dim3(FNT), 0, st, L.plan);
     } else {
         if (L.plan.vec4)
             hipLaunchKernelGGL((bbox_kernel<32, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
         else
             hipLaunchKernelGGL((bbox_kernel<32, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
-        hipLaunchKernelGGL((bbox_final_kernel<32>), dim3(1), dim3(NT), 0, st, L.plan);
+        hipLaunchKernelGGL((bbox_final_kernel<32>), dim3(1), dim3(FNT), 0, st, L.plan);
     }
     return hipGetLastError();
 }

@@ -518,6 +518,18 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     //    axis (the last block being a shorter prefix of the box).
     const int nouter = D - 1;
     const int rb_cap = std::max(1, std::min(s.rb_max, RB_MAX));
+    // Work-unit size: the schedule's, but small problems get smaller units
+    // so that there are at least about 4 per CU (never below one tile of
+    // NT * 4 vectors).
+    int64_t pe_target = s.pe_target;
+    {
+        int64_t nvec = L;
+        for (int i = 0; i < nouter; ++i)
+            nvec = (nvec > (int64_t(1) << 40) / m[i].c) ? (int64_t(1) << 40) : nvec * m[i].c;
+        const int64_t want = nvec / ((int64_t)cus * 4);
+        if (want < pe_target)
+            pe_target = std::max<int64_t>(NT * 4, want / (NT * 4) * (NT * 4));
+    }
     // Does a box of the full low axes [first, nouter) plus mm digits of
     // axis `split_axis` (or none) satisfy the magic and offset limits?
     auto fits = [&](int first, int split_axis, int64_t mm, int64_t rows) -> bool {
@@ -539,7 +551,7 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     int nfull = 0;
     int64_t RB = 1;
     for (int i = nouter - 1; i >= 0; --i) {
-        if (RB * L >= s.pe_target)
+        if (RB * L >= pe_target)
             break;
         int64_t rb2 = RB * m[i].c;
         if (rb2 > rb_cap || !fits(i, -1, 1, rb2))
@@ -549,8 +561,8 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     }
     const int a = nouter - 1 - nfull;  // next axis, candidate for the split
     int64_t mm = 1;
-    if (a >= 0 && RB * L < s.pe_target) {
-        int64_t want = (s.pe_target + RB * L - 1) / (RB * L);
+    if (a >= 0 && RB * L < pe_target) {
+        int64_t want = (pe_target + RB * L - 1) / (RB * L);
         mm = std::min<int64_t>({m[a].c - 1, want, (int64_t)rb_cap / RB});
         while (mm >= 2 && !fits(a + 1, a, mm, RB * mm))
             mm /= 2;
@@ -611,7 +623,7 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
             return TRIOT_E_UNSUPPORTED;
 
     int64_t BE = RB * L;
-    int64_t pe_cap = s.pe_target;
+    int64_t pe_cap = pe_target;
     if (RB == 1) {
         for (int k = 0; k < n; ++k)
             pe_cap = std::min<int64_t>(pe_cap, ((int64_t(1) << 31) / ((int64_t)esz * is[k])) - 1);
