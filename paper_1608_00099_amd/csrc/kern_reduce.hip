@@ -390,15 +390,9 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
                     off[k] += (int64_t)digit * P.rstride[k][i];
         }
     }
-    double acc = 0.0;
-    for (uint64_t r = r0; r < r1; ++r) {
-        double w = 1.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (k < n)
-                w *= (double)((const GLOBAL float *)(uintptr_t)P.ptr[k])[off[k]];
-        acc += w;
-        // advance the odometer over the reduced axes
+    // Eight tuples at a time: their offsets (odometer steps), then all
+    // their loads, then their weights added in order.
+    auto step = [&]() {
 #pragma unroll
         for (int i = dr - 1; i >= 0; --i) {
             if (++t[i] < P.rax[i].c || i == 0) {
@@ -414,6 +408,32 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
                     off[k] -= (int64_t)(t[i] - 1) * P.rstride[k][i];
             t[i] = 0;
         }
+    };
+    constexpr int LA = 8;
+    double acc = 0.0;
+    for (uint64_t r = r0; r < r1; r += LA) {
+        float v[LA][4];
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            const bool ok = r + (uint64_t)u < r1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < n)
+                    v[u][k] = ((const GLOBAL float *)(uintptr_t)P.ptr[k])[ok ? off[k] : P.base[k]];
+            if (r + (uint64_t)u + 1 < r1)
+                step();
+        }
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            if (r + (uint64_t)u < r1) {
+                double w = 1.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < n)
+                        w *= (double)v[u][k];
+                acc += w;
+            }
+        }
     }
     if (P.parts == 1) {
         ((float *)(uintptr_t)P.out32)[o] = (float)acc;
@@ -424,27 +444,67 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
     }
 }
 
-// One wave per output: lane l adds parts l, l + 64, .. (loads in flight
-// together), then the wave folds its 64 sums by a butterfly.  Fixed order.
+// One workgroup per output: thread t adds parts t, t + MARG_NT, .. (16
+// loads in flight per thread), then the workgroup folds in a fixed tree
+// (wave butterflies, then the waves' sums in order).
 __global__ __launch_bounds__(MARG_NT) void marginal_final_kernel(const MargPlan P)
 {
-    const uint64_t o = (uint64_t)blockIdx.x * (MARG_NT / 64) + (threadIdx.x >> 6);
-    const uint32_t lane = threadIdx.x & 63;
+    __shared__ double ws[MARG_NT / 64];
+    const uint64_t o = blockIdx.x;
+    const GLOBAL double *part = (const GLOBAL double *)((uintptr_t)P.ws + 256) + o * P.parts;
+    constexpr int K = 16;
     double acc = 0.0;
-    if (o < P.nout) {
-        const GLOBAL double *part =
-            (const GLOBAL double *)((uintptr_t)P.ws + 256) + o * P.parts;
-        for (uint32_t p = lane; p < P.parts; p += 64)
-            acc += part[p];
+    for (uint32_t b = threadIdx.x; b < P.parts; b += K * MARG_NT) {
+        double x[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const uint32_t p = b + (uint32_t)u * MARG_NT;
+            x[u] = part[p < P.parts ? p : 0u];
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+            if (b + (uint32_t)u * MARG_NT < P.parts)
+                acc += x[u];
     }
 #pragma unroll
     for (int k = 32; k >= 1; k >>= 1)
         acc += __shfl_xor(acc, k, 64);
-    if (o < P.nout && lane == 0) {
-        ((float *)(uintptr_t)P.out32)[o] = (float)acc;
+    if ((threadIdx.x & 63) == 0)
+        ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < MARG_NT / 64; ++w)
+            t += ws[w];
+        ((float *)(uintptr_t)P.out32)[o] = (float)t;
         if (P.out64)
-            ((double *)(uintptr_t)P.out64)[o] = acc;
+            ((double *)(uintptr_t)P.out64)[o] = t;
     }
+}
+
+// Few parts per output: one thread per output adds them in order, 16 loads
+// in flight at a time.
+__global__ __launch_bounds__(MARG_NT) void marginal_final_seq_kernel(const MargPlan P)
+{
+    const uint64_t o = (uint64_t)blockIdx.x * MARG_NT + threadIdx.x;
+    if (o >= P.nout)
+        return;
+    const GLOBAL double *part = (const GLOBAL double *)((uintptr_t)P.ws + 256) + o * P.parts;
+    constexpr int K = 16;
+    double acc = 0.0;
+    for (uint32_t b = 0; b < P.parts; b += K) {
+        double x[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+            x[u] = part[b + u < P.parts ? b + u : 0u];
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+            if (b + (uint32_t)u < P.parts)
+                acc += x[u];
+    }
+    ((float *)(uintptr_t)P.out32)[o] = (float)acc;
+    if (P.out64)
+        ((double *)(uintptr_t)P.out64)[o] = acc;
 }
 
 hipError_t launch_marginal(const MargLaunch &L, hipStream_t st)
@@ -460,9 +520,12 @@ hipError_t launch_marginal(const MargLaunch &L, hipStream_t st)
     case 6: hipLaunchKernelGGL((marginal_kernel<6>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
     default: hipLaunchKernelGGL((marginal_kernel<0>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
     }
-    if (L.plan.parts > 1) {
-        const uint32_t fb = (uint32_t)((L.plan.nout + MARG_NT / 64 - 1) / (MARG_NT / 64));
-        hipLaunchKernelGGL(marginal_final_kernel, dim3(fb), dim3(MARG_NT), 0, st, L.plan);
+    if (L.plan.parts >= 256) {
+        hipLaunchKernelGGL(marginal_final_kernel, dim3((uint32_t)L.plan.nout), dim3(MARG_NT), 0, st,
+                           L.plan);
+    } else if (L.plan.parts > 1) {
+        const uint32_t fb = (uint32_t)((L.plan.nout + MARG_NT - 1) / MARG_NT);
+        hipLaunchKernelGGL(marginal_final_seq_kernel, dim3(fb), dim3(MARG_NT), 0, st, L.plan);
     }
     return hipGetLastError();
 }

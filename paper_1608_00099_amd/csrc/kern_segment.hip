@@ -257,13 +257,15 @@ __device__ __forceinline__ void seg_load_half(const SegPlan &P, const int64_t of
     if constexpr (!MULTI) {
         load_words<VEC, NTL>(P, 0, off, len, h0, W.w);
     } else {
-        float v[HALF];
+        // the first two operands' loads go out together
+        float v[HALF], x[HALF];
         load_words<VEC, NTL>(P, 0, off, len, h0, v);
+        load_words<VEC, NTL>(P, 1, off, len, h0, x);
 #pragma unroll
         for (int j = 0; j < HALF; ++j)
-            W.w[j] = (double)v[j];
+            W.w[j] = (double)v[j] * (double)x[j];
 #pragma unroll
-        for (int k = 1; k < 4; ++k) {
+        for (int k = 2; k < 4; ++k) {
             if (k < (int)P.n) {
                 load_words<VEC, NTL>(P, k, off, len, h0, v);
 #pragma unroll
@@ -823,12 +825,26 @@ __global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPl
             }
         }
     }
-    __syncthreads();
+    // fold the wave first (butterflies), then one LDS atomic per wave and
+    // position: 256 same-address atomics per position would serialize
 #pragma unroll
     for (int p = 0; p < DM; ++p) {
-        if (p < D && hi[p]) {
-            atomicMin(&slo[p], lo[p]);
-            atomicMax(&shi[p], hi[p]);
+        if (p < D) {
+#pragma unroll
+            for (int k = 32; k >= 1; k >>= 1) {
+                lo[p] = min(lo[p], (uint32_t)__shfl_xor((int)lo[p], k, 64));
+                hi[p] = max(hi[p], (uint32_t)__shfl_xor((int)hi[p], k, 64));
+            }
+        }
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int p = 0; p < DM; ++p) {
+            if (p < D && hi[p]) {
+                atomicMin(&slo[p], lo[p]);
+                atomicMax(&shi[p], hi[p]);
+            }
         }
     }
     __syncthreads();
@@ -861,20 +877,36 @@ __global__ __launch_bounds__(FNT) void bbox_final_kernel(const SegPlan P)
     if (threadIdx.x < MAXD)
         pos_of[threadIdx.x] = -1;
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < nb; b += FNT) {
+    for (uint32_t b0 = 0; b0 < nb; b0 += FNT) {
+        const uint32_t b = b0 + threadIdx.x;
         uint32_t l[DM], h[DM];
 #pragma unroll
         for (int p = 0; p < DM; ++p) {
-            if (p < D) {
+            l[p] = 0xFFFFFFFFu;
+            h[p] = 0u;
+            if (p < D && b < nb) {
                 l[p] = partials[(size_t)(2 * p) * nb + b];
                 h[p] = partials[(size_t)(2 * p + 1) * nb + b];
             }
         }
+        // wave butterflies, then one LDS atomic per wave and position
 #pragma unroll
         for (int p = 0; p < DM; ++p) {
-            if (p < D && h[p]) {
-                atomicMin(&flo[p], l[p]);
-                atomicMax(&fhi[p], h[p]);
+            if (p < D) {
+#pragma unroll
+                for (int k = 32; k >= 1; k >>= 1) {
+                    l[p] = min(l[p], (uint32_t)__shfl_xor((int)l[p], k, 64));
+                    h[p] = max(h[p], (uint32_t)__shfl_xor((int)h[p], k, 64));
+                }
+            }
+        }
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int p = 0; p < DM; ++p) {
+                if (p < D && h[p]) {
+                    atomicMin(&flo[p], l[p]);
+                    atomicMax(&fhi[p], h[p]);
+                }
             }
         }
     }
