@@ -19,6 +19,7 @@ the small pad-embed) next to a plain device-copy ceiling.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -138,14 +139,21 @@ def time_steps(fns, steps, warmup):
         for e in row:
             e.record(s)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        for i, f in enumerate(fns):
-            ev[k][i].record(s)
-            f()
-        ev[k][len(fns)].record(s)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # No garbage collection while the host enqueues the timed steps: a
+    # collector pause would leave the device idle inside a timed launch.
+    gc.collect()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        for k in range(steps):
+            for i, f in enumerate(fns):
+                ev[k][i].record(s)
+                f()
+            ev[k][len(fns)].record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        gc.enable()
     total = ev[0][0].elapsed_time(ev[-1][len(fns)])
     per = [[ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(steps)] for i in range(len(fns))]
     return total / steps, wall / steps * 1e3, per
