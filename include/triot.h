@@ -300,6 +300,14 @@ triot_status triot_schedule_set(triot_op op, int n_tensors, int d, const int64_t
                                 const int64_t *bases, const void *params,
                                 const triot_schedule *schedule);
 
+/* Set the launch schedule of a batch (cache policy, blocks per CU, box
+ * rows, unit size; vec_max and unit_order are ignored: batch items use
+ * 4-byte lanes and contiguous unit ranges).  Releases the planned table
+ * and graph: the next triot_apply_batched plans and captures afresh.
+ * The default is non-temporal loads and stores, 8 blocks per CU,
+ * 8192-element units, 1024 box rows.  TRIOT_E_INVALID for a knob out of range. */
+triot_status triot_batch_set_schedule(triot_batch *handle, const triot_schedule *schedule);
+
 /* ---- diagnostics -------------------------------------------------------- */
 
 const char *triot_status_string(triot_status status);
@@ -329,6 +337,9 @@ typedef struct triot_plan_info {
     int cache_policy;        /* 0 normal, 1 non-temporal loads and stores,
                                 2 non-temporal loads only */
     int unit_order;          /* 0 contiguous ranges, 1 round-robin */
+    int row_tail;            /* inner extent not a multiple of vec: the words in
+                                each row's last vector, which is moved back to
+                                end at the row end (0: rows are whole vectors) */
 } triot_plan_info;
 
 triot_status triot_plan_describe(triot_op op, int n_tensors, int d, const int64_t *shapes,

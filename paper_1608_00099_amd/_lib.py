@@ -63,7 +63,7 @@ class PlanInfo(ctypes.Structure):
                 ("box_rows", ctypes.c_int64), ("units", ctypes.c_int64),
                 ("blocks", ctypes.c_int), ("threads", ctypes.c_int), ("unroll", ctypes.c_int),
                 ("inner_unit", ctypes.c_int), ("cache_policy", ctypes.c_int),
-                ("unit_order", ctypes.c_int)]
+                ("unit_order", ctypes.c_int), ("row_tail", ctypes.c_int)]
 
 
 class Schedule(ctypes.Structure):
@@ -82,7 +82,8 @@ class TriotError(RuntimeError):
 _lib = None
 
 EXPORTS = ["triot_apply", "triot_workspace_size", "triot_batch_create", "triot_batch_destroy",
-           "triot_apply_batched", "triot_batch_launch", "triot_batch_info", "triot_autotune", "triot_tune_reset", "triot_schedule_set",
+           "triot_apply_batched", "triot_batch_launch", "triot_batch_info", "triot_batch_set_schedule",
+           "triot_autotune", "triot_tune_reset", "triot_schedule_set",
            "triot_status_string", "triot_divmod_magic", "triot_plan_describe"]
 
 
@@ -112,6 +113,8 @@ def lib():
     L.triot_batch_launch.argtypes = [P, P]
     L.triot_batch_info.restype = I
     L.triot_batch_info.argtypes = [P, pI64, ctypes.POINTER(I), ctypes.POINTER(I)]
+    L.triot_batch_set_schedule.restype = I
+    L.triot_batch_set_schedule.argtypes = [P, ctypes.POINTER(Schedule)]
     L.triot_autotune.restype = I
     L.triot_autotune.argtypes = [I, I, I, pI64, pI64, pP, pI64, P, P, P, SZ, P, ctypes.c_char_p]
     L.triot_tune_reset.restype = None
@@ -222,6 +225,10 @@ def triot_batch_create():
 
 def triot_batch_destroy(handle) -> None:
     lib().triot_batch_destroy(handle)
+
+
+def triot_batch_set_schedule(handle, schedule) -> int:
+    return lib().triot_batch_set_schedule(handle, ctypes.byref(schedule))
 
 
 def triot_apply_batched(op, items, params, handle, stream) -> int:

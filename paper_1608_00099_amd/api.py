@@ -336,6 +336,12 @@ class Batch:
         st = L.triot_apply_batched(op, marshalled, params, self._h, _stream(dev))
         _check(st, "apply_batched")
 
+    def set_schedule(self, cache_policy=1, blocks_per_cu=8, box_rows_max=1024, unit_elems=8192):
+        """Set the launch schedule of this batch (the next apply re-plans and
+        re-captures); the defaults are the library's."""
+        sch = L.Schedule(1, cache_policy, blocks_per_cu, box_rows_max, unit_elems, 0)
+        _check(L.triot_batch_set_schedule(self._h, sch), "batch_set_schedule")
+
     def launch(self, device=None):
         """Replay the last planned batch on the current stream (no
         re-validation: the caller keeps the same buffers alive)."""
@@ -389,7 +395,7 @@ def describe(op, shapes, counter=None, ptrs=None, bases=None, params=None):
             "units": info.units, "blocks": info.blocks, "threads": info.threads,
             "unroll": info.unroll, "inner_unit": info.inner_unit,
             "cache_policy": info.cache_policy, "unit_order": info.unit_order,
-            "n_tensors": len(shapes)}
+            "row_tail": info.row_tail, "n_tensors": len(shapes)}
 
 
 _CO_OP = {0: 0, 1: 1, 2: 2, 3: 3, 6: 4, 7: 5}   # public op -> kernel template op
@@ -411,5 +417,6 @@ def kernel_name(op, plan):
     rows1 = "true" if plan["box_rows"] == 1 else "false"
     unit = "true" if plan["inner_unit"] else "false"
     cp = 0 if op == L.OP_INDEX else plan["cache_policy"]
-    return "void triot::coiter_kernel<%d, %d, %d, %s, %s, %d>(triot::CoPlan)" % (
-        _CO_OP[op], plan["vec"], plan["unroll"], rows1, unit, cp)
+    rag = "true" if plan.get("row_tail") else "false"
+    return "void triot::coiter_kernel<%d, %d, %d, %s, %s, %d, %s>(triot::CoPlan)" % (
+        _CO_OP[op], plan["vec"], plan["unroll"], rows1, unit, cp, rag)

@@ -345,6 +345,7 @@ extern "C" triot_status triot_plan_describe(triot_op op, int n_tensors, int d, c
     info->inner_unit = L.unit ? 1 : 0;
     info->cache_policy = L.cache;
     info->unit_order = (int)P.interleave;
+    info->row_tail = P.tskip ? (int)(P.vec - P.tskip) : 0;
     return TRIOT_OK;
 }
 
@@ -504,8 +505,26 @@ extern "C" triot_status triot_schedule_set(triot_op op, int n_tensors, int d,
 
 // ---- batched form --------------------------------------------------------
 
+// Batch items are planned with 4-byte lanes (one code path for any
+// alignment) and never get the small-problem unit shrink (the batch as a
+// whole fills the device).  Default: non-temporal loads and stores, 8
+// workgroups per CU, 8192-element units (the fastest of cache policy x
+// {2,4,8} workgroups x {2048..16384} elements on 4096 ragged pads, timed
+// cold).
+static Sched batch_default_sched()
+{
+    Sched s;
+    s.vec_max = 1;
+    s.pe_target = 8192;
+    s.cache = 1;
+    s.blocks_per_cu = 8;
+    s.small_units = false;
+    return s;
+}
+
 struct triot_batch {
     std::vector<int64_t> sig;     // what the captured graph was built for
+    Sched sched = batch_default_sched();
     CoPlan *d_plans = nullptr;
     uint32_t *d_ustart = nullptr;
     hipGraph_t graph = nullptr;
@@ -550,6 +569,26 @@ extern "C" void triot_batch_destroy(triot_batch *handle)
     if (handle->cap)
         (void)hipStreamDestroy(handle->cap);
     delete handle;
+}
+
+extern "C" triot_status triot_batch_set_schedule(triot_batch *handle, const triot_schedule *schedule)
+{
+    if (!handle || !schedule)
+        return TRIOT_E_INVALID;
+    Sched s = batch_default_sched();
+    s.cache = schedule->cache_policy;
+    s.blocks_per_cu = schedule->blocks_per_cu;
+    s.rb_max = schedule->box_rows_max;
+    s.pe_target = schedule->unit_elems;
+    s.order = 0;
+    if (!sched_valid(s))
+        return TRIOT_E_INVALID;
+    handle->sched = s;
+    batch_release(handle);        // the next apply plans and captures afresh
+    handle->device = -1;
+    handle->units = 0;
+    handle->blocks = 0;
+    return TRIOT_OK;
 }
 
 extern "C" triot_status triot_batch_info(const triot_batch *handle, int64_t *n_units, int *n_blocks,
@@ -631,15 +670,14 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
     // Plan every item (4-byte lanes keep one code path for any alignment).
     batch_release(handle);
     handle->replayed = 0;
-    Sched s;
-    s.vec_max = 1;
-    s.pe_target = 4096;
+    const Sched s = handle->sched;
     const int cus = device_cus();
     std::vector<CoPlan> plans;
     std::vector<uint32_t> ustart;
     plans.reserve((size_t)n_items);
     ustart.push_back(0);
     uint64_t total = 0;
+    uint32_t rows_max = 0;
     for (int i = 0; i < n_items; ++i) {
         const Request &r = reqs[(size_t)i];
         if (r.npoints == 0)
@@ -648,6 +686,8 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
         triot_status st = plan_coiter(r, s, cus, &L);
         if (st != TRIOT_OK)
             return st;
+        if (L.plan.RB > 1)
+            rows_max = std::max(rows_max, L.plan.RB);
         plans.push_back(L.plan);
         total += L.plan.nunits;
         if (total >= (uint64_t(1) << 32))
@@ -660,7 +700,7 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
         handle->blocks = 0;
         return TRIOT_OK;
     }
-    int blocks = (int)std::min<uint64_t>(total, (uint64_t)cus * 4);
+    int blocks = (int)std::min<uint64_t>(total, (uint64_t)cus * std::max(1, s.blocks_per_cu));
     if (blocks > 8)
         blocks = (blocks + 7) / 8 * 8;
     handle->blocks = blocks;
@@ -691,8 +731,18 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
         batch_release(handle);
         return TRIOT_E_DEVICE;
     }
-    hipError_t le = launch_batched(co_op_of(op), handle->d_plans, handle->d_ustart, nitems,
-                                   (uint32_t)total, blocks, handle->cap);
+    BatchLaunch B;
+    B.plans = handle->d_plans;
+    B.ustart = handle->d_ustart;
+    B.nitems = nitems;
+    B.total = (uint32_t)total;
+    B.rows_max = rows_max;
+    B.blocks = blocks;
+    B.cus = cus;
+    B.cache = s.cache;
+    B.launched = blocks;
+    hipError_t le = launch_batched(co_op_of(op), B, handle->cap);
+    handle->blocks = B.launched;
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(handle->cap, &graph);
     if (le != hipSuccess || ce != hipSuccess || !graph) {

@@ -64,6 +64,12 @@ struct CoPlan {
     uint32_t predmask;   // bit k: operand k only where t lies inside its window
     uint32_t esz;        // bytes per vector element (4 * vec)
     uint32_t vec;
+    // Ragged rows: when the inner extent is not a multiple of vec, each row
+    // ends in a vector moved back by tshift bytes so that it ends at the row
+    // end; of its vec words only the last vec - tskip are new (tskip = 0:
+    // rows are whole vectors).
+    uint32_t tshift;
+    uint32_t tskip;
     uint32_t unit;       // 1 when every inner stride is 1
     uint32_t interleave; // unit order: 0 a contiguous range of units per
                          // workgroup, 1 units dealt round-robin

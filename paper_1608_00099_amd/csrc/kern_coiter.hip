@@ -67,6 +67,24 @@ template <class T, int CP> __device__ __forceinline__ void gstore(gchar *p, uint
         *a = v;
 }
 
+// Store of a ragged row's last vector: only its words from `skip` on are
+// new (the others belong to the vector before it, stored by another lane).
+// 1 <= skip < V.
+template <class T, int CP>
+__device__ __forceinline__ void gstore_tail(gchar *p, uint32_t off, T v, uint32_t skip)
+{
+    if constexpr (sizeof(T) > 4) {
+        constexpr int V = sizeof(T) / 4;
+        typedef __typeof__(v[0] + 0) W;
+#pragma unroll
+        for (int c = 1; c < V; ++c) {
+            W w = v[c];
+            if ((uint32_t)c >= skip)
+                gstore<W, CP>(p, off + 4u * c, w);
+        }
+    }
+}
+
 template <int V> struct Vec;
 template <> struct Vec<1> {
     typedef uint32_t U;
@@ -82,18 +100,27 @@ template <> struct Vec<4> {
     typedef float F __attribute__((ext_vector_type(4), aligned(4)));
 };
 
+// The box-row table in LDS, sized per launch (dynamic shared memory) so that
+// small boxes leave room for more resident workgroups: per operand, `rs`
+// pre-adjusted byte offsets of the box rows (operand-major), then, for the
+// predicated ops, `rs` row masks (bits 0-7: the row lies inside operand k's
+// window; bits 8-31: the row's digit on the split axis).
+extern __shared__ uint32_t lds_rows[];
+
 struct RowTable {
-    uint32_t off[MAXT][RB_MAX];   // pre-adjusted byte offsets of each box row
-    uint32_t mask[RB_MAX];        // bits 0-7: the row lies inside operand k's window;
-                                  // bits 8-31: the row's digit on the split axis
+    uint32_t *t;
+    uint32_t rs;               // row stride: the plan's rows per box
+    __device__ __forceinline__ uint32_t off(int k, uint32_t r) const { return t[(uint32_t)k * rs + r]; }
+    __device__ __forceinline__ uint32_t mask(uint32_t n, uint32_t r) const { return t[n * rs + r]; }
 };
 
 // Tabulate the box rows: decode each row over the low axes and store, per
 // operand, row offset * 4 - row * L * istride * esz (bytes; row offsets are
 // in 4-byte words, the inner axis in vectors of esz bytes) so that element
 // e of the box sits at table[row] + e * istride * esz bytes from the box
-// base.
-__device__ void fill_table(const CoPlan &P, RowTable &T)
+// base.  Row masks are stored when PRED.
+template <bool PRED>
+__device__ void fill_table(const CoPlan &P, const RowTable &T)
 {
     const uint32_t n = P.n, nhigh = P.nhigh, nlow = P.nlow;
     for (uint32_t r = threadIdx.x; r < P.RB; r += NT) {
@@ -125,9 +152,10 @@ __device__ void fill_table(const CoPlan &P, RowTable &T)
 #pragma unroll
         for (int k = 0; k < MAXT; ++k)
             if (k < (int)n)
-                T.off[k][r] = rel[k] * 4u - r * P.L * P.istride[k] * P.esz;
+                T.t[(uint32_t)k * T.rs + r] = rel[k] * 4u - r * P.L * P.istride[k] * P.esz;
         // t now holds the outermost low digit (the split axis' digit if split)
-        T.mask[r] = mask | (t << 8);
+        if (PRED)
+            T.t[n * T.rs + r] = mask | (t << 8);
     }
 }
 
@@ -141,7 +169,7 @@ template <> struct OpInfo<CO_INDEX> { static constexpr int N = MAXT; static cons
 template <> struct OpInfo<CO_XPYX_MZ> { static constexpr int N = 3; static constexpr bool PRED = false; };
 
 // Process one work unit (a part of one box).
-template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP>
+template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP, bool RAG>
 __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const RowTable &T)
 {
     typedef typename Vec<V>::U VU;
@@ -228,9 +256,11 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
     }
 
     // ---- per element ----
+    const uint32_t lastj = P.L - 1;
     for (uint32_t e = e0 + threadIdx.x; e < e1; e += NT * U) {
         uint32_t ev[U];
         bool valid[U];
+        bool tl[U];              // a ragged row's last vector
         uint32_t off[N][U];
         uint32_t pm[U];
         uint32_t jj[U];
@@ -249,9 +279,10 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                 j = x - row * P.L;
             }
             jj[u] = j;
+            tl[u] = RAG && j == lastj;
             pm[u] = 0xFFFFFFFFu;
             if (OpInfo<OP>::PRED) {
-                const uint32_t rm = ROWS1 ? 0xFFu : T.mask[row];
+                const uint32_t rm = ROWS1 ? 0xFFu : T.mask(n, row);
                 const uint32_t dig = rm >> 8;
                 uint32_t m = himask & rm & 0xFFu;
 #pragma unroll
@@ -263,14 +294,17 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 if (k < (int)n) {
-                    uint32_t rel = ROWS1 ? 0u : T.off[k][row];
+                    uint32_t rel = ROWS1 ? 0u : T.off(k, row);
                     uint32_t xe = ROWS1 ? (x - e0) : x;
-                    off[k][u] = rel + xe * isb[k];
+                    off[k][u] = rel + xe * isb[k] - (tl[u] ? P.tshift : 0u);
                 }
             }
         }
 
         if constexpr (OP == CO_COPY) {
+            // A ragged row's last vector is stored whole: the words it shares
+            // with the vector before it get the same source words again (the
+            // destination is either disjoint from the source or the source).
             VU v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -305,7 +339,10 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
             for (int u = 0; u < U; ++u)
                 if (valid[u]) {
                     VF prod = y[u] * z[u];       // rounded once (no contraction)
-                    gstore<VF, CP>(bp[0], off[0][u], x[u] + prod);
+                    if (tl[u])
+                        gstore_tail<VF, CP>(bp[0], off[0][u], x[u] + prod, P.tskip);
+                    else
+                        gstore<VF, CP>(bp[0], off[0][u], x[u] + prod);
                 }
         } else if constexpr (OP == CO_XPYX_MZ) {
             VF x[U], y[U], z[U];
@@ -322,7 +359,10 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                     // (x + y*x) - z, each operation rounded once
                     VF prod = y[u] * x[u];
                     VF sum = x[u] + prod;
-                    gstore<VF, CP>(bp[0], off[0][u], sum - z[u]);
+                    if (tl[u])
+                        gstore_tail<VF, CP>(bp[0], off[0][u], sum - z[u], P.tskip);
+                    else
+                        gstore<VF, CP>(bp[0], off[0][u], sum - z[u]);
                 }
         } else if constexpr (OP == CO_MUL) {
             VF a[U], b[U];
@@ -334,8 +374,14 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                 }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (valid[u])
-                    gstore<VF, CP>(bp[0], off[0][u], a[u] * b[u]);
+                if (valid[u]) {
+                    // x may be y or z (in place): the shared words are not
+                    // stored twice
+                    if (tl[u])
+                        gstore_tail<VF, CP>(bp[0], off[0][u], a[u] * b[u], P.tskip);
+                    else
+                        gstore<VF, CP>(bp[0], off[0][u], a[u] * b[u]);
+                }
         } else if constexpr (OP == CO_MUL_ADJ) {
             // operands: 0 ga, 1 gb, 2 gout, 3 a, 4 b
             VF g[U], a[U], b[U];
@@ -382,12 +428,12 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
     }
 }
 
-template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP>
+template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP, bool RAG>
 __global__ __launch_bounds__(NT) void coiter_kernel(const CoPlan P)
 {
-    __shared__ RowTable T;
+    const RowTable T{lds_rows, P.RB};
     if (!ROWS1) {
-        fill_table(P, T);
+        fill_table<OpInfo<OP>::PRED>(P, T);
         __syncthreads();
     }
     const uint32_t lb = logical_block();
@@ -395,12 +441,12 @@ __global__ __launch_bounds__(NT) void coiter_kernel(const CoPlan P)
     if (P.interleave) {
         // round-robin: at any moment the grid sweeps one window of memory
         for (uint64_t u = lb; u < P.nunits; u += g)
-            run_unit<OP, V, U, ROWS1, UNIT, CP>(P, (uint32_t)u, T);
+            run_unit<OP, V, U, ROWS1, UNIT, CP, RAG>(P, (uint32_t)u, T);
     } else {
         const uint32_t u0 = (uint32_t)(((uint64_t)lb * P.nunits) / g);
         const uint32_t u1 = (uint32_t)(((uint64_t)(lb + 1) * P.nunits) / g);
         for (uint32_t u = u0; u < u1; ++u)
-            run_unit<OP, V, U, ROWS1, UNIT, CP>(P, u, T);
+            run_unit<OP, V, U, ROWS1, UNIT, CP, RAG>(P, u, T);
     }
 }
 
@@ -410,12 +456,11 @@ __global__ __launch_bounds__(NT) void coiter_kernel(const CoPlan P)
 // item's first unit); every workgroup walks a contiguous range of units and
 // re-tabulates its box rows whenever the range enters a new item.
 // ---------------------------------------------------------------------
-template <int OP, int U>
+template <int OP, int U, int CP>
 __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ plans,
                                                      const uint32_t *__restrict__ ustart,
                                                      uint32_t nitems, uint32_t total)
 {
-    __shared__ RowTable T;
     const uint32_t lb = logical_block();
     const uint32_t g = gridDim.x;
     const uint32_t u0 = (uint32_t)(((uint64_t)lb * total) / g);
@@ -450,23 +495,24 @@ __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ 
                 dst[i] = src[i];
             __syncthreads();
             if (Ps.RB > 1)
-                fill_table(Ps, T);
+                fill_table<OpInfo<OP>::PRED>(Ps, RowTable{lds_rows, Ps.RB});
             __syncthreads();
             loaded = true;
         }
         const CoPlan &P = Ps;
+        const RowTable T{lds_rows, P.RB};
         const bool rows1 = P.RB == 1;
         const uint32_t lu = u - first;
         if (rows1) {
             if (P.unit)
-                run_unit<OP, 1, U, true, true, CP_NORMAL>(P, lu, T);
+                run_unit<OP, 1, U, true, true, CP, false>(P, lu, T);
             else
-                run_unit<OP, 1, U, true, false, CP_NORMAL>(P, lu, T);
+                run_unit<OP, 1, U, true, false, CP, false>(P, lu, T);
         } else {
             if (P.unit)
-                run_unit<OP, 1, U, false, true, CP_NORMAL>(P, lu, T);
+                run_unit<OP, 1, U, false, true, CP, false>(P, lu, T);
             else
-                run_unit<OP, 1, U, false, false, CP_NORMAL>(P, lu, T);
+                run_unit<OP, 1, U, false, false, CP, false>(P, lu, T);
         }
     }
 }
@@ -475,17 +521,63 @@ __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ 
 // Host-side launchers
 // ---------------------------------------------------------------------
 
-template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP>
+// Workgroups of `kern` that fit on one CU at once with `lds` bytes of
+// dynamic LDS (0 if the runtime cannot tell).  `cache` is the calling
+// kernel's own memo, by LDS size in KiB (the query asks for the rounded-up
+// size).
+static int resident_per_cu(const void *kern, size_t lds, int (&cache)[64])
+{
+    const size_t kib = (lds + 1023) / 1024;
+    if (kib < 64 && cache[kib] > 0)
+        return cache[kib];
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, kib * 1024) != hipSuccess)
+        return 0;
+    if (kib < 64 && nb > 0)
+        cache[kib] = nb;
+    return nb;
+}
+
+// A persistent grid (each workgroup owns a fixed share of the work) larger
+// than what fits at once would run its last workgroups after the others:
+// keep it within the resident capacity (a multiple of 8 for whole XCDs).
+static int clamp_resident(int blocks, int per_cu, int cus)
+{
+    if (per_cu <= 0 || cus <= 0)
+        return blocks;
+    const int cap = per_cu * cus;
+    return blocks > cap ? cap : blocks;
+}
+
+template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP, bool RAG = false>
 static hipError_t go(const CoLaunch &L, hipStream_t st)
 {
-    hipLaunchKernelGGL((coiter_kernel<OP, V, U, ROWS1, UNIT, CP>), dim3(L.blocks), dim3(NT), 0,
-                       st, L.plan);
+    static int occ[64];
+    const auto kern = coiter_kernel<OP, V, U, ROWS1, UNIT, CP, RAG>;
+    const size_t lds =
+        ROWS1 ? 0 : (size_t)L.plan.RB * (L.plan.n + (OpInfo<OP>::PRED ? 1 : 0)) * 4u;
+    const int blocks =
+        clamp_resident(L.blocks, resident_per_cu(reinterpret_cast<const void *>(kern), lds, occ),
+                       L.cus);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, L.plan);
     return hipGetLastError();
 }
 
 template <int OP, int V, int U, int CP>
 static hipError_t pick_rows(const CoLaunch &L, hipStream_t st)
 {
+    if (L.plan.tskip) {
+        // ragged rows: planned only for vectors of unit-stride rows, for
+        // ops without window predicates
+        if constexpr (V > 1 && !OpInfo<OP>::PRED && OP != CO_INDEX) {
+            if (!L.unit)
+                return hipErrorInvalidValue;
+            return L.rows1 ? go<OP, V, U, true, true, CP, true>(L, st)
+                           : go<OP, V, U, false, true, CP, true>(L, st);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (L.rows1)
         return L.unit ? go<OP, V, U, true, true, CP>(L, st) : go<OP, V, U, true, false, CP>(L, st);
     return L.unit ? go<OP, V, U, false, true, CP>(L, st) : go<OP, V, U, false, false, CP>(L, st);
@@ -530,28 +622,36 @@ hipError_t launch_coiter(int co_op, const CoLaunch &L, hipStream_t st)
     }
 }
 
-hipError_t launch_batched(int co_op, const CoPlan *plans, const uint32_t *ustart, uint32_t nitems,
-                          uint32_t total, int blocks, hipStream_t st)
+template <int OP, int CP>
+static void go_batched(BatchLaunch &B, hipStream_t st)
+{
+    static int occ[64];
+    const auto kern = batched_kernel<OP, 4, CP>;
+    const size_t lds = (size_t)B.rows_max * (OpInfo<OP>::N + (OpInfo<OP>::PRED ? 1 : 0)) * 4u;
+    B.launched = clamp_resident(
+        B.blocks, resident_per_cu(reinterpret_cast<const void *>(kern), lds, occ), B.cus);
+    hipLaunchKernelGGL(kern, dim3(B.launched), dim3(NT), lds, st, B.plans, B.ustart, B.nitems,
+                       B.total);
+}
+
+template <int OP>
+static void pick_batched(BatchLaunch &B, hipStream_t st)
+{
+    switch (B.cache) {
+    case CP_NONTEMP_LS: go_batched<OP, CP_NONTEMP_LS>(B, st); break;
+    case CP_NONTEMP_L: go_batched<OP, CP_NONTEMP_L>(B, st); break;
+    default: go_batched<OP, CP_NORMAL>(B, st); break;
+    }
+}
+
+hipError_t launch_batched(int co_op, BatchLaunch &B, hipStream_t st)
 {
     switch (co_op) {
-    case CO_COPY:
-        hipLaunchKernelGGL((batched_kernel<CO_COPY, 4>), dim3(blocks), dim3(NT), 0, st, plans, ustart,
-                           nitems, total);
-        break;
-    case CO_FILL:
-        hipLaunchKernelGGL((batched_kernel<CO_FILL, 4>), dim3(blocks), dim3(NT), 0, st, plans, ustart,
-                           nitems, total);
-        break;
-    case CO_MUL_ACC:
-        hipLaunchKernelGGL((batched_kernel<CO_MUL_ACC, 4>), dim3(blocks), dim3(NT), 0, st, plans,
-                           ustart, nitems, total);
-        break;
-    case CO_MUL:
-        hipLaunchKernelGGL((batched_kernel<CO_MUL, 4>), dim3(blocks), dim3(NT), 0, st, plans, ustart,
-                           nitems, total);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    case CO_COPY: pick_batched<CO_COPY>(B, st); break;
+    case CO_FILL: pick_batched<CO_FILL>(B, st); break;
+    case CO_MUL_ACC: pick_batched<CO_MUL_ACC>(B, st); break;
+    case CO_MUL: pick_batched<CO_MUL>(B, st); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

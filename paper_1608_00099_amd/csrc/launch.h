@@ -8,8 +8,19 @@
 namespace triot {
 
 hipError_t launch_coiter(int co_op, const CoLaunch &L, hipStream_t st);
-hipError_t launch_batched(int co_op, const CoPlan *plans, const uint32_t *ustart, uint32_t nitems,
-                          uint32_t total, int blocks, hipStream_t st);
+// One persistent launch over a device table of item plans.
+struct BatchLaunch {
+    const CoPlan *plans;      // device: the item plans
+    const uint32_t *ustart;   // device: each item's first work unit, then the total
+    uint32_t nitems;
+    uint32_t total;           // work units over all items
+    uint32_t rows_max;        // largest rows per box among items with RB > 1 (0: none)
+    int blocks;               // requested grid (clamped to what fits at once)
+    int cus;
+    int cache;                // cache policy
+    int launched;             // out: the grid launched
+};
+hipError_t launch_batched(int co_op, BatchLaunch &B, hipStream_t st);
 hipError_t launch_moments(const SegLaunch &L, hipStream_t st);
 hipError_t launch_moments_adj(const SegLaunch &L, hipStream_t st);
 int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4);

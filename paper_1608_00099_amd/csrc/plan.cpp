@@ -473,24 +473,35 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     //    so that a vector never straddles two rows.  Addresses need only be
     //    4-byte aligned: multi-dword global accesses take any dword address
     //    on CDNA.  Strides and bases stay in 4-byte words.
+    //    Ragged rows (an inner extent of at least 2 widths that is not a
+    //    multiple of the width) still take the width when the op reads and
+    //    writes every operand on the whole counter (no window predicates):
+    //    each row's last vector is moved back to end at the row end, reads
+    //    words of the vector before it again and stores only its new words.
     const Ax &in = m[D - 1];
+    const bool ragged_ok = r.op == TRIOT_OP_COPY || r.op == TRIOT_OP_MUL_ACC ||
+                           r.op == TRIOT_OP_MUL || r.op == TRIOT_OP_XPYX_MZ;
     int vec = 1;
+    int64_t rtail = 0;   // words in a row's last vector (0: whole vectors)
     if (r.op != TRIOT_OP_INDEX) {
         for (int v = std::min(4, std::max(1, s.vec_max)); v > 1; v >>= 1) {
-            bool ok = (in.c % v) == 0 && in.c / v >= 2;
+            const bool whole = (in.c % v) == 0 && in.c / v >= 2;
+            const bool rag = !whole && ragged_ok && in.c > v;
+            bool ok = whole || rag;
             for (int k = 0; k < n && ok; ++k) {
                 if (in.S[k] != 1 || ((uintptr_t)r.ptr[k] % 4) != 0)
                     ok = false;
-                if (in.B[k] != -1 && in.B[k] % v != 0)
+                if (in.B[k] != -1 && (rag || in.B[k] % v != 0))
                     ok = false;
             }
             if (ok) {
                 vec = v;
+                rtail = whole ? 0 : in.c % v;
                 break;
             }
         }
     }
-    const int64_t L = in.c / vec;
+    const int64_t L = (in.c + vec - 1) / vec;
     const uint32_t esz = 4u * vec;
     if (L >= (int64_t(1) << 32))
         return TRIOT_E_UNSUPPORTED;
@@ -527,7 +538,7 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
         for (int i = 0; i < nouter; ++i)
             nvec = (nvec > (int64_t(1) << 40) / m[i].c) ? (int64_t(1) << 40) : nvec * m[i].c;
         const int64_t want = nvec / ((int64_t)cus * 4);
-        if (want < pe_target)
+        if (s.small_units && want < pe_target)
             pe_target = std::max<int64_t>(NT * 4, want / (NT * 4) * (NT * 4));
     }
     // Does a box of the full low axes [first, nouter) plus mm digits of
@@ -653,6 +664,8 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     P.nunits = (uint32_t)nunits;
     P.esz = esz;
     P.vec = (uint32_t)vec;
+    P.tskip = rtail ? (uint32_t)(vec - rtail) : 0u;
+    P.tshift = P.tskip * 4u;
     P.unit = unit ? 1u : 0u;
     P.interleave = s.order ? 1u : 0u;
     P.split = split ? 1u : 0u;
@@ -715,6 +728,7 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
         blocks = (blocks + 7) / 8 * 8;
     out->blocks = std::max(blocks, 1);
     out->unroll = 4;
+    out->cus = cus;
     out->cache = s.cache;
     out->rows1 = (RB == 1);
     out->unit = unit;

@@ -18,6 +18,7 @@ struct Sched {
                             // stores, 2 non-temporal loads only
     int blocks_per_cu = 4;  // persistent workgroups per CU
     int order = 0;          // unit order: 0 blocked ranges, 1 round-robin
+    bool small_units = true;  // shrink units of small problems (not for batch items)
     int rb_max = RB_MAX;    // rows per box (LDS table) upper bound
     int pe_target = 8192;   // elements per work unit
 };
@@ -40,7 +41,8 @@ struct CoLaunch {
     CoPlan plan;
     int dims;                 // the merged counter (before any split)
     int64_t extents[MAXD];    // its extents, inner axis in elements
-    int blocks;
+    int blocks;               // requested grid (the launch keeps it within what fits at once)
+    int cus;                  // compute units of the device planned for
     int unroll;               // elements per thread per step (fixed: 4)
     int cache;                // cache policy (Sched::cache)
     bool rows1;     // RB == 1

@@ -146,6 +146,28 @@ def test_plan_drops_extent_one_and_merges_full_axes():
     assert p["dims"] == 1 and p["extents"] == [1]
 
 
+def test_plan_ragged_rows():
+    # an inner extent that is not a multiple of 4: 4-word lanes, each row's
+    # last vector holding 39 % 4 = 3 new words
+    p = api.describe(L.OP_MUL_ACC, [(57, 59, 37, 15, 39), (62, 59, 44, 22, 51),
+                                    (59, 64, 40, 19, 41)])
+    assert p["vec"] == 4 and p["row_tail"] == 3 and p["extents"][-1] == 39
+    p = api.describe(L.OP_COPY, [(10, 11), (6, 9)], counter=(6, 9))
+    assert p["vec"] == 4 and p["row_tail"] == 1 and p["extents"] == [6, 9]
+    # 3 words: 2-word lanes, the last one moved back by a word
+    p = api.describe(L.OP_MUL, [(7, 3), (7, 3), (7, 5)])
+    assert p["vec"] == 2 and p["row_tail"] == 1
+    # whole vectors report no tail
+    p = api.describe(L.OP_MUL_ACC, [(5, 40), (5, 44), (5, 48)])
+    assert p["vec"] == 4 and p["row_tail"] == 0
+    # the predicated ops (window bounds inside the counter) keep 1-word
+    # lanes on ragged rows, as does a row of at most one vector
+    p = api.describe(L.OP_EMBED_FILL, [(9, 11), (7, 9)], params=L.CopyParams(4))
+    assert p["vec"] == 1 and p["row_tail"] == 0
+    p = api.describe(L.OP_MUL_ACC, [(5, 2), (5, 3), (5, 3)])
+    assert p["vec"] == 1 and p["row_tail"] == 0
+
+
 def test_plan_box_split_limits():
     # very short rows: the box tabulates several low axes (bounded table)
     p = api.describe(L.OP_COPY, [(9, 5, 13, 21, 14, 6, 3, 25)] * 1 + [(10, 6, 14, 22, 15, 7, 4, 26)],
