@@ -117,6 +117,49 @@ def autotune_all(launches, cache_path=None):
     return out
 
 
+def problems_of(launches):
+    """The (op, operands) of every launch, as the schedule calls take them."""
+    from paper_1608_00099_amd import _lib as L
+    out = []
+    for name, op, fn, nbytes, it in launches:
+        if op == L.OP_COPY:
+            out.append(dict(op=op, tensors=[it["dst"], it["src"]], counter=it["src_s"],
+                            params=L.CopyParams(4)))
+        else:
+            out.append(dict(op=op, tensors=[it["x"], it["y"], it["z"]]))
+    return out
+
+
+def sequence_tune(launches, path=None):
+    """Refine the schedules in the sequence they run in (see tune.py) and
+    keep them in `path` (JSON) for runs that reuse the tuning."""
+    from paper_1608_00099_amd import tune
+    scheds = tune.tune_sequence(problems_of(launches), [x[2] for x in launches], log=log)
+    if path:
+        with open(path, "w") as f:
+            json.dump({x[0]: s for x, s in zip(launches, scheds)}, f)
+    return scheds
+
+
+def pin_sequence(launches, path):
+    from paper_1608_00099_amd import api
+    with open(path) as f:
+        saved = json.load(f)
+    for (name, *_), p in zip(launches, problems_of(launches)):
+        if name in saved:
+            api.schedule_set(p["op"], p["tensors"], counter=p.get("counter"),
+                             params=p.get("params"), **saved[name])
+
+
+def tuned_summary(launches):
+    out = {}
+    for name, op, fn, nbytes, it in launches:
+        p = plan_of(op, it)[0]
+        out[name] = {"cache": p["cache_policy"], "blocks": p["blocks"], "vec": p["vec"],
+                     "box_rows": p["box_rows"], "row_tail": p["row_tail"]}
+    return out
+
+
 def time_steps(fns, steps, warmup):
     """Time exactly `steps` steps of the launch sequence `fns`.  HIP events
     recorded on the stream the kernels run on (the library enqueues on
@@ -492,6 +535,8 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="schedule cache file: loaded if it exists (no tuning), else "
                          "written after tuning (so profiled runs launch the same kernels)")
+    ap.add_argument("--no-seq-tune", action="store_true",
+                    help="skip the in-sequence refinement of the tuned schedules")
     ap.add_argument("--cpu-log2", type=float, default=25.5,
                     help="log2 elements per tensor of the CPU oracle sample")
     args = ap.parse_args()
@@ -514,15 +559,16 @@ def main():
     log("allocating the d=2..8 sweep")
     sw = Sweep(dev)
     launches = sw.launches()
-    tuned = {}
+    seq_path = args.tune_cache + ".seq.json" if args.tune_cache else None
     if not args.no_tune and not reuse:
         log("autotuning the %d launch schedules" % len(launches))
-        tuned = autotune_all(launches, args.tune_cache)
-    elif reuse:
-        tuned = {name: dict(zip(("cache", "blocks", "vec", "box_rows"),
-                                (lambda p: (p["cache_policy"], p["blocks"], p["vec"],
-                                            p["box_rows"]))(plan_of(op, it)[0])))
-                 for name, op, fn, nbytes, it in launches}
+        autotune_all(launches, args.tune_cache)
+        if not args.no_seq_tune:
+            log("refining the schedules in sequence")
+            sequence_tune(launches, seq_path)
+    elif reuse and seq_path and os.path.exists(seq_path) and not args.no_seq_tune:
+        pin_sequence(launches, seq_path)
+    tuned = tuned_summary(launches)
     step_bytes = sum(x[3] for x in launches)
     fns = [x[2] for x in launches]
     log("timing %d steps after %d warm-up steps" % (args.steps, args.warmup))

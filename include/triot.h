@@ -300,6 +300,14 @@ triot_status triot_schedule_set(triot_op op, int n_tensors, int d, const int64_t
                                 const int64_t *bases, const void *params,
                                 const triot_schedule *schedule);
 
+/* The schedule triot_apply uses for this problem: the one pinned or tuned
+ * for its plan signature, else the defaults.  Same arguments and errors
+ * as triot_schedule_set; no device work. */
+triot_status triot_schedule_get(triot_op op, int n_tensors, int d, const int64_t *shapes,
+                                const int64_t *counter_shape, void *const *tensors,
+                                const int64_t *bases, const void *params,
+                                triot_schedule *schedule);
+
 /* Set the launch schedule of a batch (cache policy, blocks per CU, box
  * rows, unit size; vec_max and unit_order are ignored: batch items use
  * 4-byte lanes and contiguous unit ranges).  Releases the planned table

@@ -83,7 +83,7 @@ _lib = None
 
 EXPORTS = ["triot_apply", "triot_workspace_size", "triot_batch_create", "triot_batch_destroy",
            "triot_apply_batched", "triot_batch_launch", "triot_batch_info", "triot_batch_set_schedule",
-           "triot_autotune", "triot_tune_reset", "triot_schedule_set",
+           "triot_autotune", "triot_tune_reset", "triot_schedule_set", "triot_schedule_get",
            "triot_status_string", "triot_divmod_magic", "triot_plan_describe"]
 
 
@@ -121,6 +121,8 @@ def lib():
     L.triot_tune_reset.argtypes = []
     L.triot_schedule_set.restype = I
     L.triot_schedule_set.argtypes = [I, I, I, pI64, pI64, pP, pI64, P, ctypes.POINTER(Schedule)]
+    L.triot_schedule_get.restype = I
+    L.triot_schedule_get.argtypes = [I, I, I, pI64, pI64, pP, pI64, P, ctypes.POINTER(Schedule)]
     L.triot_status_string.restype = ctypes.c_char_p
     L.triot_status_string.argtypes = [I]
     L.triot_divmod_magic.restype = I
@@ -215,6 +217,17 @@ def triot_schedule_set(op, n_tensors, d, shapes, counter_shape, tensors, bases, 
     return lib().triot_schedule_set(int(op), int(n_tensors), int(d), shapes_a, counter_a,
                                     _ptr_array(tensors), bases_a, _params_ptr(params),
                                     ctypes.byref(schedule))
+
+
+def triot_schedule_get(op, n_tensors, d, shapes, counter_shape, tensors, bases, params):
+    shapes_a = _i64_array([v for s in shapes for v in s] if d else [])
+    counter_a = _i64_array(counter_shape) if counter_shape is not None else None
+    bases_a = _i64_array(bases) if bases is not None else None
+    sch = Schedule()
+    st = lib().triot_schedule_get(int(op), int(n_tensors), int(d), shapes_a, counter_a,
+                                  _ptr_array(tensors), bases_a, _params_ptr(params),
+                                  ctypes.byref(sch))
+    return st, sch
 
 
 def triot_batch_create():

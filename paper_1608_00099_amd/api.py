@@ -376,6 +376,18 @@ def schedule_set(op, tensors, shapes=None, counter=None, bases=None, params=None
     _check(st, "schedule_set")
 
 
+def schedule_get(op, tensors, shapes=None, counter=None, bases=None, params=None):
+    """The launch schedule triot_apply uses for this exact problem (pinned,
+    tuned or default), as a dict of schedule_set's keyword arguments."""
+    dev, shapes = _prep(tensors, shapes)
+    st, sch = L.triot_schedule_get(op, len(tensors), len(shapes[0]), shapes, counter,
+                                   [_ptr(t) for t in tensors], bases, params)
+    _check(st, "schedule_get")
+    return {"vec_max": sch.vec_max, "cache_policy": sch.cache_policy,
+            "blocks_per_cu": sch.blocks_per_cu, "box_rows_max": sch.box_rows_max,
+            "unit_elems": sch.unit_elems, "unit_order": sch.unit_order}
+
+
 def tune_reset():
     """Forget every tuned or pinned schedule (the defaults apply again)."""
     L.triot_tune_reset()

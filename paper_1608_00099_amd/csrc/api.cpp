@@ -503,6 +503,29 @@ extern "C" triot_status triot_schedule_set(triot_op op, int n_tensors, int d,
     return TRIOT_OK;
 }
 
+extern "C" triot_status triot_schedule_get(triot_op op, int n_tensors, int d,
+                                           const int64_t *shapes, const int64_t *counter_shape,
+                                           void *const *tensors, const int64_t *bases,
+                                           const void *params, triot_schedule *schedule)
+{
+    if (!schedule)
+        return TRIOT_E_INVALID;
+    Request r;
+    triot_status st = validate(op, n_tensors, d, shapes, counter_shape, tensors, bases, params, &r);
+    if (st != TRIOT_OK)
+        return st;
+    if (co_op_of(op) < 0)
+        return TRIOT_E_UNSUPPORTED;
+    const Sched s = sched_for(r);
+    schedule->vec_max = s.vec_max;
+    schedule->cache_policy = s.cache;
+    schedule->blocks_per_cu = s.blocks_per_cu;
+    schedule->box_rows_max = s.rb_max;
+    schedule->unit_elems = s.pe_target;
+    schedule->unit_order = s.order;
+    return TRIOT_OK;
+}
+
 // ---- batched form --------------------------------------------------------
 
 // Batch items are planned with 4-byte lanes (one code path for any

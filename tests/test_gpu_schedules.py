@@ -180,3 +180,63 @@ def test_vector_lanes_on_word_aligned_rows(case, cp):
     api.mul_acc_(gx, gy, gz)
     got = host(gx)
     assert bits_equal(got, want), first_mismatch(got, want)
+
+
+def test_sequence_tuning_pins_schedules_and_keeps_results():
+    """tune_sequence pins a schedule per problem of a sequence; the
+    sequence still gives the oracle's bits afterwards."""
+    from paper_1608_00099_amd import tune
+    announce("sequence tuning")
+    src_s, dst_s = (37, 41, 39), (40, 45, 44)
+    xs, ys, zs = (33, 20, 39), (35, 21, 40), (33, 22, 41)
+    rng = np.random.default_rng(160)
+    src = rng.standard_normal(src_s).astype(np.float32)
+    x = rng.standard_normal(xs).astype(np.float32)
+    y = rng.standard_normal(ys).astype(np.float32)
+    z = rng.standard_normal(zs).astype(np.float32)
+    g, gs = torch.zeros(dst_s, device="cuda"), dev(src)
+    gx, gy, gz = dev(x), dev(y), dev(z)
+    runs = [0]
+
+    def step_copy():
+        api.pad_embed_into(g, gs)
+
+    def step_mul_acc():
+        runs[0] += 1
+        api.mul_acc_(gx, gy, gz)
+
+    problems = [dict(op=L.OP_COPY, tensors=[g, gs], counter=src_s, params=L.CopyParams(4)),
+                dict(op=L.OP_MUL_ACC, tensors=[gx, gy, gz])]
+    scheds = tune.tune_sequence(problems, [step_copy, step_mul_acc], steps=3,
+                                knobs=(("vec_max", (4, 1)), ("cache_policy", (0, 1))))
+    assert len(scheds) == 2
+    for p, s in zip(problems, scheds):
+        assert api.schedule_get(p["op"], p["tensors"], counter=p.get("counter"),
+                                params=p.get("params")) == s
+    want = np.zeros(dst_s, dtype=np.float32)
+    oracle.copy(src_s, want.reshape(-1), dst_s, src.reshape(-1), src_s)
+    assert bits_equal(host(g), want), first_mismatch(host(g), want)
+    # x was updated `runs` times: replay that on the oracle
+    gx.copy_(dev(x))
+    api.mul_acc_(gx, gy, gz)
+    want = x.copy()
+    oracle.mul_acc(xs, want.reshape(-1), xs, y.reshape(-1), ys, z.reshape(-1), zs)
+    assert bits_equal(host(gx), want), first_mismatch(host(gx), want)
+    assert runs[0] > 1
+
+
+def test_schedule_get_reports_defaults_and_pins():
+    announce("schedule_get")
+    x = torch.zeros((8, 40), device="cuda")
+    y = torch.zeros((8, 40), device="cuda")
+    z = torch.zeros((8, 40), device="cuda")
+    s = api.schedule_get(L.OP_MUL_ACC, [x, y, z])
+    assert s == {"vec_max": 4, "cache_policy": 1, "blocks_per_cu": 4, "box_rows_max": 1024,
+                 "unit_elems": 8192, "unit_order": 0}
+    _pin(L.OP_MUL_ACC, [x, y, z], [(8, 40)] * 3, None, (2, 2, 8, 16, 1024, 1))
+    s = api.schedule_get(L.OP_MUL_ACC, [x, y, z])
+    assert s == {"vec_max": 2, "cache_policy": 2, "blocks_per_cu": 8, "box_rows_max": 16,
+                 "unit_elems": 1024, "unit_order": 1}
+    with pytest.raises(L.TriotError) as e:
+        api.schedule_get(L.OP_MOMENTS, [x], params=L.MomentsParams(0, 0))
+    assert e.value.status == L.E_UNSUPPORTED
