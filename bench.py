@@ -16,7 +16,13 @@ workload, and per-configuration figures for the other parts of the hot path
 (moments, batched padding for FFT convolution, the differentiable pipeline,
 the small pad-embed) next to a plain device-copy ceiling.
 
+The sweep's launch schedules are pinned from a JSON file written by an
+earlier `--retune --save-schedules` run on an MI355X (the library's
+autotuner per launch, then the in-sequence refinement of tune.py), so that
+every run and its profiles launch the same kernels; `--retune` tunes afresh.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+                       [--retune] [--save-schedules FILE] [--schedules FILE] [--no-tune]
 """
 import argparse
 import gc
@@ -30,6 +36,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# The sweep's launch schedules as tuned on an MI355X (bench.py --retune
+# --save-schedules): pinned by default so that every run, and the profiles
+# of it, launch the same kernels.
+SCHEDULES = os.path.join(ROOT, "paper_1608_00099_amd", "tuned", "sweep_d2-8_mi355x.json")
 
 
 def log(*a):
@@ -99,22 +109,12 @@ def plan_of(op, it):
     return p, api.kernel_name(op, p)
 
 
-def autotune_all(launches, cache_path=None):
+def autotune_all(launches):
     """Let the library's autotuner pick each launch's schedule (it times the
     candidates with HIP events on these very buffers)."""
     from paper_1608_00099_amd import api
-    from paper_1608_00099_amd import _lib as L
-    out = {}
-    for name, op, fn, nbytes, it in launches:
-        if op == L.OP_COPY:
-            api.autotune(op, [it["dst"], it["src"]], counter=it["src_s"], params=L.CopyParams(4),
-                         cache_path=cache_path)
-        else:
-            api.autotune(op, [it["x"], it["y"], it["z"]], cache_path=cache_path)
-        plan, kname = plan_of(op, it)
-        out[name] = {"cache": plan["cache_policy"], "blocks": plan["blocks"], "vec": plan["vec"],
-                     "box_rows": plan["box_rows"]}
-    return out
+    for p in problems_of(launches):
+        api.autotune(p["op"], p["tensors"], counter=p.get("counter"), params=p.get("params"))
 
 
 def problems_of(launches):
@@ -130,25 +130,35 @@ def problems_of(launches):
     return out
 
 
-def sequence_tune(launches, path=None):
-    """Refine the schedules in the sequence they run in (see tune.py) and
-    keep them in `path` (JSON) for runs that reuse the tuning."""
+def sequence_tune(launches):
+    """Refine the schedules in the sequence they run in (see tune.py)."""
     from paper_1608_00099_amd import tune
-    scheds = tune.tune_sequence(problems_of(launches), [x[2] for x in launches], log=log)
-    if path:
-        with open(path, "w") as f:
-            json.dump({x[0]: s for x, s in zip(launches, scheds)}, f)
-    return scheds
+    tune.tune_sequence(problems_of(launches), [x[2] for x in launches], log=log)
 
 
-def pin_sequence(launches, path):
+def save_schedules(launches, path):
+    """Write the schedule every launch runs with (name -> schedule_set's
+    keywords)."""
+    from paper_1608_00099_amd import api
+    out = {}
+    for (name, *_), p in zip(launches, problems_of(launches)):
+        out[name] = api.schedule_get(p["op"], p["tensors"], counter=p.get("counter"),
+                                     params=p.get("params"))
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+
+
+def pin_schedules(launches, path):
     from paper_1608_00099_amd import api
     with open(path) as f:
         saved = json.load(f)
+    missing = [x[0] for x in launches if x[0] not in saved]
+    if missing:
+        raise SystemExit("%s has no schedule for %s" % (path, missing))
     for (name, *_), p in zip(launches, problems_of(launches)):
-        if name in saved:
-            api.schedule_set(p["op"], p["tensors"], counter=p.get("counter"),
-                             params=p.get("params"), **saved[name])
+        api.schedule_set(p["op"], p["tensors"], counter=p.get("counter"),
+                         params=p.get("params"), **saved[name])
 
 
 def tuned_summary(launches):
@@ -215,19 +225,21 @@ def cpu_baseline(log2_target):
         src_s, dst_s = inputs.cfg2_pad_shapes(d, log2_target)
         src = inputs.uniform(2, src_s, 90, d)
         dst = np.zeros(prod(dst_s), dtype=np.float32)
-        t0 = time.perf_counter()
-        oracle.copy(src_s, dst, dst_s, src.reshape(-1), src_s)
-        total_s += time.perf_counter() - t0
-        total_bytes += 8 * prod(src_s)
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.copy(src_s, dst, dst_s, src.reshape(-1), src_s)
+            total_s += time.perf_counter() - t0
+            total_bytes += 8 * prod(src_s)
         del src, dst
         xs, ys, zs = inputs.cfg2_inter_shapes(d, log2_target)
         x = inputs.uniform(2, xs, 91, d).reshape(-1)
         y = inputs.uniform(2, ys, 92, d).reshape(-1)
         z = inputs.uniform(2, zs, 93, d).reshape(-1)
-        t0 = time.perf_counter()
-        oracle.mul_acc(xs, x, xs, y, ys, z, zs)
-        total_s += time.perf_counter() - t0
-        total_bytes += 16 * prod(xs)
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.mul_acc(xs, x, xs, y, ys, z, zs)
+            total_s += time.perf_counter() - t0
+            total_bytes += 16 * prod(xs)
         del x, y, z
         log("cpu oracle d=%d done (%.1f s so far)" % (d, total_s))
     return total_bytes / total_s / 1e9, total_s
@@ -530,14 +542,19 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only", choices=EXTRAS, default=None,
                     help="time one secondary configuration alone (for profiling)")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="skip the autotuner (default schedules)")
-    ap.add_argument("--tune-cache", default=None,
-                    help="schedule cache file: loaded if it exists (no tuning), else "
-                         "written after tuning (so profiled runs launch the same kernels)")
+    ap.add_argument("--schedules", default=SCHEDULES,
+                    help="JSON of the launch schedules to pin (launch name -> schedule), "
+                         "written by --retune --save-schedules")
+    ap.add_argument("--retune", action="store_true",
+                    help="ignore --schedules: run the autotuner on every launch, then refine "
+                         "the schedules in sequence")
     ap.add_argument("--no-seq-tune", action="store_true",
-                    help="skip the in-sequence refinement of the tuned schedules")
-    ap.add_argument("--cpu-log2", type=float, default=25.5,
+                    help="with --retune: skip the in-sequence refinement")
+    ap.add_argument("--save-schedules", default=None,
+                    help="write the schedules the sweep ran with to this JSON file")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="the library's default schedules (no pinning, no tuning)")
+    ap.add_argument("--cpu-log2", type=float, default=26,
                     help="log2 elements per tensor of the CPU oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -545,9 +562,6 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    reuse = bool(args.tune_cache) and os.path.exists(args.tune_cache)
-    if reuse:
-        os.environ["TRIOT_TUNE_CACHE"] = os.path.abspath(args.tune_cache)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_1608_00099_amd import _lib as L
@@ -559,15 +573,21 @@ def main():
     log("allocating the d=2..8 sweep")
     sw = Sweep(dev)
     launches = sw.launches()
-    seq_path = args.tune_cache + ".seq.json" if args.tune_cache else None
-    if not args.no_tune and not reuse:
+    if args.no_tune:
+        how = "library defaults"
+    elif args.retune or not os.path.exists(args.schedules):
         log("autotuning the %d launch schedules" % len(launches))
-        autotune_all(launches, args.tune_cache)
+        autotune_all(launches)
+        how = "autotuned per launch"
         if not args.no_seq_tune:
             log("refining the schedules in sequence")
-            sequence_tune(launches, seq_path)
-    elif reuse and seq_path and os.path.exists(seq_path) and not args.no_seq_tune:
-        pin_sequence(launches, seq_path)
+            sequence_tune(launches)
+            how += ", refined in sequence"
+    else:
+        pin_schedules(launches, args.schedules)
+        how = "pinned from %s" % os.path.relpath(args.schedules, ROOT)
+    if args.save_schedules:
+        save_schedules(launches, args.save_schedules)
     tuned = tuned_summary(launches)
     step_bytes = sum(x[3] for x in launches)
     fns = [x[2] for x in launches]
@@ -607,8 +627,9 @@ def main():
         log("CPU oracle baseline (sample 2^%g elements per tensor)" % args.cpu_log2)
         gbs, secs = cpu_baseline(args.cpu_log2)
         cpu = {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": "the same d=2..8 copy + x+=y*z recipe at 2^%g elements per tensor, "
-                         "single-threaded C oracle, %.1f s" % (args.cpu_log2, secs)}
+               "sample": "the same d=2..8 copy + x+=y*z recipe at 2^%g elements per tensor "
+                         "(the full step at 2^26), each launch run twice, single-threaded C "
+                         "oracle, %.1f s" % (args.cpu_log2, secs)}
 
     ext = None
     if not args.no_extras:
@@ -628,6 +649,7 @@ def main():
         "cpu_baseline": cpu,
         "per_op": per_op,
         "tuned": tuned,
+        "schedules": how,
         "extras": ext,
         "kernel_source": src_hash,
     }
