@@ -216,33 +216,97 @@ def time_steps(fns, steps, warmup):
 # CPU baseline: the oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
 
-def cpu_baseline(log2_target):
+def _slabs(counter, shapes, bases, pieces):
+    """Split a counter into at least `pieces` windows along its leading
+    axes: [(sub-counter, per-operand bases)], each a plain oracle call."""
+    d = len(counter)
+    k, n = 0, 1
+    while k < d - 1 and n < pieces:
+        n *= counter[k]
+        k += 1
+    out = []
+    for f in range(n):
+        t, r = [0] * k, f
+        for i in range(k - 1, -1, -1):
+            t[i] = r % counter[i]
+            r //= counter[i]
+        sub = tuple([1] * k + list(counter[k:])) if k else tuple(counter)
+        bs = []
+        for s_, b in zip(shapes, bases):
+            stride, off = 1, 0
+            for i in range(d - 1, -1, -1):
+                if i < k:
+                    off += t[i] * stride
+                stride *= s_[i]
+            bs.append(b + off)
+        out.append((sub, bs))
+    return out
+
+
+def cpu_baseline(log2_target, threads):
+    """The oracle on the sweep recipe: one single-threaded pass, then three
+    passes with `threads` threads, each taking windows of the leading
+    counter axes (plain oracle calls; ctypes releases the interpreter lock
+    while the C code runs)."""
+    import concurrent.futures as cf
     import numpy as np
     import oracle
     from paper_1608_00099_amd import inputs
-    total_bytes, total_s = 0, 0.0
+    single_bytes, single_s = 0, 0.0
+    par_bytes, par_s = 0, [0.0, 0.0, 0.0]
+    pool = cf.ThreadPoolExecutor(max_workers=threads)
+
+    def run_par(calls):
+        parts = [calls[t::threads] for t in range(threads)]
+        t0 = time.perf_counter()
+        list(pool.map(lambda cs: [c() for c in cs], parts))
+        return time.perf_counter() - t0
+
     for d in range(2, 9):
         src_s, dst_s = inputs.cfg2_pad_shapes(d, log2_target)
-        src = inputs.uniform(2, src_s, 90, d)
+        src = inputs.uniform(2, src_s, 90, d).reshape(-1)
         dst = np.zeros(prod(dst_s), dtype=np.float32)
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            oracle.copy(src_s, dst, dst_s, src.reshape(-1), src_s)
-            total_s += time.perf_counter() - t0
-            total_bytes += 8 * prod(src_s)
-        del src, dst
+        t0 = time.perf_counter()
+        oracle.copy(src_s, dst, dst_s, src, src_s)
+        single_s += time.perf_counter() - t0
+        single_bytes += 8 * prod(src_s)
+        calls = [(lambda sub=sub, b=b: oracle.copy(sub, dst, dst_s, src, src_s, b[0], b[1]))
+                 for sub, b in _slabs(src_s, [dst_s, src_s], [0, 0], 4 * threads)]
+        for r in range(3):
+            par_s[r] += run_par(calls)
+        par_bytes += 8 * prod(src_s)
+        del src, dst, calls
         xs, ys, zs = inputs.cfg2_inter_shapes(d, log2_target)
         x = inputs.uniform(2, xs, 91, d).reshape(-1)
         y = inputs.uniform(2, ys, 92, d).reshape(-1)
         z = inputs.uniform(2, zs, 93, d).reshape(-1)
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            oracle.mul_acc(xs, x, xs, y, ys, z, zs)
-            total_s += time.perf_counter() - t0
-            total_bytes += 16 * prod(xs)
-        del x, y, z
-        log("cpu oracle d=%d done (%.1f s so far)" % (d, total_s))
-    return total_bytes / total_s / 1e9, total_s
+        t0 = time.perf_counter()
+        oracle.mul_acc(xs, x, xs, y, ys, z, zs)
+        single_s += time.perf_counter() - t0
+        single_bytes += 16 * prod(xs)
+        calls = [(lambda sub=sub, b=b: oracle.mul_acc(sub, x, xs, y, ys, z, zs, b[0], b[1], b[2]))
+                 for sub, b in _slabs(xs, [xs, ys, zs], [0, 0, 0], 4 * threads)]
+        for r in range(3):
+            par_s[r] += run_par(calls)
+        par_bytes += 16 * prod(xs)
+        del x, y, z, calls
+        log("cpu oracle d=%d done (%.1f s single, %.1f s threaded so far)"
+            % (d, single_s, sum(par_s)))
+    pool.shutdown()
+    par = sorted(par_bytes / t / 1e9 for t in par_s)
+    return {"single": (single_bytes / single_s / 1e9, single_s),
+            "threaded": (par[1], par[0], par[2], sum(par_s))}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # ---------------------------------------------------------------------------
@@ -554,6 +618,8 @@ def main():
                     help="write the schedules the sweep ran with to this JSON file")
     ap.add_argument("--no-tune", action="store_true",
                     help="the library's default schedules (no pinning, no tuning)")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="threads of the threaded CPU oracle timing (at most the CPUs present)")
     ap.add_argument("--cpu-log2", type=float, default=26,
                     help="log2 elements per tensor of the CPU oracle sample")
     args = ap.parse_args()
@@ -624,12 +690,20 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        log("CPU oracle baseline (sample 2^%g elements per tensor)" % args.cpu_log2)
-        gbs, secs = cpu_baseline(args.cpu_log2)
-        cpu = {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        log("CPU oracle baseline (2^%g elements per tensor, 1 and %d threads)"
+            % (args.cpu_log2, threads))
+        r = cpu_baseline(args.cpu_log2, threads)
+        gbs1, secs1 = r["single"]
+        med, lo, hi, secs_t = r["threaded"]
+        cpu = {"value": round(med, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
                "sample": "the same d=2..8 copy + x+=y*z recipe at 2^%g elements per tensor "
-                         "(the full step at 2^26), each launch run twice, single-threaded C "
-                         "oracle, %.1f s" % (args.cpu_log2, secs)}
+                         "(the full step at 2^26), C oracle on %s: %d threads each taking "
+                         "windows of the leading counter axes, median of 3 passes (%.1f s in "
+                         "all)" % (args.cpu_log2, cpu_model(), threads, secs_t),
+               "min": round(lo, 3), "max": round(hi, 3),
+               "single_thread": {"value": round(gbs1, 3), "cores": 1,
+                                 "seconds": round(secs1, 2)}}
 
     ext = None
     if not args.no_extras:
