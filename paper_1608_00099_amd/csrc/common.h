@@ -146,6 +146,14 @@ struct ConvPlan {
 struct MargPlan {
     uint32_t n, dk, dr;       // operands, kept axes, reduced axes
     uint32_t parts;
+    // Walk of a part: mode 0 one element at a time; mode 1 four at a time
+    // (the innermost reduced axis is every operand's last axis, extent a
+    // multiple of 4, part boundaries multiples of 4); mode 2 interleaved
+    // (one reduced axis, contiguous in every operand: lane l of a wave
+    // takes elements chunk * clen + l + 64 s, so a wave's loads are
+    // coalesced).
+    uint32_t mode;
+    uint32_t clen;            // mode 2: elements per chunk (64 lanes)
     uint64_t nout;            // kept tuples (< 2^32)
     uint64_t nred;            // reduced tuples
     AxisDiv kax[MAXD];        // kept extents, outermost first

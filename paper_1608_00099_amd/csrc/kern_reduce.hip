@@ -337,9 +337,39 @@ uint32_t conv_lds_words() { return CONV_LDS_WORDS - 3 * 8; }
 // ---------------------------------------------------------------------
 constexpr int MARG_NT = 256;
 
-// RD > 0: exactly RD reduced axes, known at compile time (the odometer in
-// registers); RD == 0: any number.
-template <int RD>
+// Kept tuple o -> the element offsets of its reduced sub-box's origin.
+__device__ __forceinline__ void marginal_kept(const MargPlan &P, uint32_t o, int64_t off[4])
+{
+    const int n = (int)P.n, dk = (int)P.dk;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        off[k] = P.base[k];
+    uint32_t q = o;
+    for (int i = dk - 1; i >= 0; --i) {
+        uint32_t digit;
+        if (i == 0) {
+            digit = q;
+        } else {
+            const uint32_t qq = rdiv_u32(q, P.kax[i]);
+            digit = q - qq * P.kax[i].c;
+            q = qq;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < n)
+                off[k] += (int64_t)digit * P.kstride[k][i];
+    }
+}
+
+typedef float mf4 __attribute__((ext_vector_type(4), aligned(4)));
+
+// Thread (o, p) adds part p of kept tuple o's reduced sub-box in
+// lexicographic order.  RD > 0: exactly RD reduced axes, known at compile
+// time (the odometer in registers); RD == 0: any number.  W = 4: the
+// innermost reduced axis is every operand's last axis with an extent that
+// is a multiple of 4, and the walk loads four consecutive elements at a
+// time (added in order, as one at a time would).
+template <int RD, int W>
 __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
 {
     const uint64_t gid = (uint64_t)blockIdx.x * MARG_NT + threadIdx.x;
@@ -348,33 +378,14 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
         return;
     const uint32_t o = (uint32_t)(gid % P.nout);
     const uint32_t p = (uint32_t)(gid / P.nout);
-    const int n = (int)P.n, dk = (int)P.dk, dr = RD > 0 ? RD : (int)P.dr;
+    const int n = (int)P.n, dr = RD > 0 ? RD : (int)P.dr;
     constexpr int TN = RD > 0 ? RD : MAXD;
     int64_t off[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        off[k] = P.base[k];
-    // kept tuple o
-    {
-        uint32_t q = o;
-        for (int i = dk - 1; i >= 0; --i) {
-            uint32_t digit;
-            if (i == 0) {
-                digit = q;
-            } else {
-                const uint32_t qq = rdiv_u32(q, P.kax[i]);
-                digit = q - qq * P.kax[i].c;
-                q = qq;
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (k < n)
-                    off[k] += (int64_t)digit * P.kstride[k][i];
-        }
-    }
-    // part p of the reduced sub-box: flat range [r0, r1)
-    const uint64_t r0 = (uint64_t)p * P.nred / P.parts;
-    const uint64_t r1 = (uint64_t)(p + 1) * P.nred / P.parts;
+    marginal_kept(P, o, off);
+    // part p of the reduced sub-box: flat range [r0, r1), in steps of W
+    const uint64_t units = P.nred / W;
+    const uint64_t r0 = (uint64_t)p * units / P.parts * W;
+    const uint64_t r1 = (uint64_t)(p + 1) * units / P.parts * W;
     uint32_t t[TN];
     {
         uint64_t q = r0;
@@ -390,48 +401,64 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
                     off[k] += (int64_t)digit * P.rstride[k][i];
         }
     }
-    // Eight tuples at a time: their offsets (odometer steps), then all
+    // Eight steps at a time: their offsets (odometer steps), then all
     // their loads, then their weights added in order.
     auto step = [&]() {
 #pragma unroll
         for (int i = dr - 1; i >= 0; --i) {
-            if (++t[i] < P.rax[i].c || i == 0) {
+            const uint32_t inc = (i == dr - 1) ? (uint32_t)W : 1u;
+            t[i] += inc;
+            if (t[i] < P.rax[i].c || i == 0) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     if (k < n)
-                        off[k] += P.rstride[k][i];
+                        off[k] += (int64_t)inc * P.rstride[k][i];
                 break;
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (k < n)
-                    off[k] -= (int64_t)(t[i] - 1) * P.rstride[k][i];
+                    off[k] -= (int64_t)(t[i] - inc) * P.rstride[k][i];
             t[i] = 0;
         }
     };
     constexpr int LA = 8;
     double acc = 0.0;
-    for (uint64_t r = r0; r < r1; r += LA) {
-        float v[LA][4];
+    for (uint64_t r = r0; r < r1; r += LA * W) {
+        float v[LA][4][W];
 #pragma unroll
         for (int u = 0; u < LA; ++u) {
-            const bool ok = r + (uint64_t)u < r1;
+            const bool ok = r + (uint64_t)u * W < r1;
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (k < n)
-                    v[u][k] = ((const GLOBAL float *)(uintptr_t)P.ptr[k])[ok ? off[k] : P.base[k]];
-            if (r + (uint64_t)u + 1 < r1)
+            for (int k = 0; k < 4; ++k) {
+                if (k < n) {
+                    const GLOBAL float *pk = (const GLOBAL float *)(uintptr_t)P.ptr[k];
+                    if constexpr (W == 4) {
+                        const mf4 x = *(const GLOBAL mf4 *)(pk + (ok ? off[k] : P.base[k]));
+                        v[u][k][0] = x.x;
+                        v[u][k][1] = x.y;
+                        v[u][k][2] = x.z;
+                        v[u][k][3] = x.w;
+                    } else {
+                        v[u][k][0] = pk[ok ? off[k] : P.base[k]];
+                    }
+                }
+            }
+            if (r + (uint64_t)(u + 1) * W < r1)
                 step();
         }
 #pragma unroll
         for (int u = 0; u < LA; ++u) {
-            if (r + (uint64_t)u < r1) {
-                double w = 1.0;
+            if (r + (uint64_t)u * W < r1) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (k < n)
-                        w *= (double)v[u][k];
-                acc += w;
+                for (int e = 0; e < W; ++e) {
+                    double w = 1.0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (k < n)
+                            w *= (double)v[u][k][e];
+                    acc += w;
+                }
             }
         }
     }
@@ -442,6 +469,52 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
     } else {
         ((double *)((char *)(uintptr_t)P.ws + 256))[(uint64_t)o * P.parts + p] = acc;
     }
+}
+
+// One contiguous reduced run per kept tuple (one reduced axis, stride 1 in
+// every operand): part p = 64 c + l of output o is lane l of chunk c, the
+// elements c * clen + l + 64 s of the run, so every load of a wave reads
+// 64 consecutive elements.  Each lane adds its elements in order; the
+// parts are then combined in order by the final kernels.
+__global__ __launch_bounds__(MARG_NT) void marginal_inter_kernel(const MargPlan P)
+{
+    const uint64_t gid = (uint64_t)blockIdx.x * MARG_NT + threadIdx.x;
+    const uint64_t total = P.nout * P.parts;
+    if (gid >= total)
+        return;
+    const uint32_t o = (uint32_t)(gid / P.parts);     // a wave shares its output
+    const uint32_t p = (uint32_t)(gid - (uint64_t)o * P.parts);
+    const int n = (int)P.n;
+    int64_t off[4];
+    marginal_kept(P, o, off);
+    const uint64_t c0 = (uint64_t)(p >> 6) * P.clen;
+    const uint64_t end = min(c0 + P.clen, P.nred);
+    constexpr int LA = 8;
+    double acc = 0.0;
+    for (uint64_t r = c0 + (p & 63u); r < end; r += 64 * LA) {
+        float v[LA][4];
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            const uint64_t e = r + (uint64_t)u * 64;
+            const uint64_t ee = e < end ? e : c0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < n)
+                    v[u][k] = ((const GLOBAL float *)(uintptr_t)P.ptr[k])[off[k] + (int64_t)ee];
+        }
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            if (r + (uint64_t)u * 64 < end) {
+                double w = 1.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < n)
+                        w *= (double)v[u][k];
+                acc += w;
+            }
+        }
+    }
+    ((double *)((char *)(uintptr_t)P.ws + 256))[(uint64_t)o * P.parts + p] = acc;
 }
 
 // One workgroup per output: thread t adds parts t, t + MARG_NT, .. (16
@@ -507,19 +580,29 @@ __global__ __launch_bounds__(MARG_NT) void marginal_final_seq_kernel(const MargP
         ((double *)(uintptr_t)P.out64)[o] = acc;
 }
 
+template <int W> static void go_marginal(const MargLaunch &L, uint32_t blocks, hipStream_t st)
+{
+    switch (L.plan.dr) {
+    case 1: hipLaunchKernelGGL((marginal_kernel<1, W>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 2: hipLaunchKernelGGL((marginal_kernel<2, W>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 3: hipLaunchKernelGGL((marginal_kernel<3, W>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 4: hipLaunchKernelGGL((marginal_kernel<4, W>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 5: hipLaunchKernelGGL((marginal_kernel<5, W>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    case 6: hipLaunchKernelGGL((marginal_kernel<6, W>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    default: hipLaunchKernelGGL((marginal_kernel<0, W>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
+    }
+}
+
 hipError_t launch_marginal(const MargLaunch &L, hipStream_t st)
 {
     const uint64_t total = L.plan.nout * L.plan.parts;
     const uint32_t blocks = (uint32_t)((total + MARG_NT - 1) / MARG_NT);
-    switch (L.plan.dr) {
-    case 1: hipLaunchKernelGGL((marginal_kernel<1>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
-    case 2: hipLaunchKernelGGL((marginal_kernel<2>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
-    case 3: hipLaunchKernelGGL((marginal_kernel<3>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
-    case 4: hipLaunchKernelGGL((marginal_kernel<4>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
-    case 5: hipLaunchKernelGGL((marginal_kernel<5>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
-    case 6: hipLaunchKernelGGL((marginal_kernel<6>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
-    default: hipLaunchKernelGGL((marginal_kernel<0>), dim3(blocks), dim3(MARG_NT), 0, st, L.plan); break;
-    }
+    if (L.plan.mode == 2)
+        hipLaunchKernelGGL(marginal_inter_kernel, dim3(blocks), dim3(MARG_NT), 0, st, L.plan);
+    else if (L.plan.mode == 1)
+        go_marginal<4>(L, blocks, st);
+    else
+        go_marginal<1>(L, blocks, st);
     if (L.plan.parts >= 256) {
         hipLaunchKernelGGL(marginal_final_kernel, dim3((uint32_t)L.plan.nout), dim3(MARG_NT), 0, st,
                            L.plan);

@@ -948,55 +948,104 @@ triot_status plan_marginal(const Request &r, int cus, MargLaunch *out)
     MargPlan &P = out->plan;
     const int n = r.n, d = r.d;
     const uint32_t km = ((const triot_marginal_params *)r.params)->keep_mask;
-    int dk = 0, dr = 0;
-    uint64_t nout = 1, nred = 1;
+    // Non-trivial axes in order, then adjacent axes of the same kind (both
+    // kept or both reduced) merged where every operand is contiguous across
+    // them: the kept tuple's flat index and the set of reduced tuples are
+    // unchanged, and a merged reduced run is walked in one stride.
+    struct MAx {
+        int64_t c;
+        int64_t st[MAXT];
+        bool keep;
+    };
+    MAx ax[MAXD];
+    int na = 0;
     for (int i = 0; i < d; ++i) {
         const int64_t c = r.counter[i];
         if (c == 1)
             continue;             // contributes nothing to any offset or index
-        if (c >= (int64_t(1) << 32))
-            return TRIOT_E_UNSUPPORTED;
-        int64_t st[MAXT];
+        MAx a;
+        a.c = c;
+        a.keep = ((km >> i) & 1u) != 0;
         for (int k = 0; k < n; ++k) {
             int64_t v = 1;
-            for (int j = i + 1; j < d; ++j)
-                v *= r.shape[k][j];
-            st[k] = v;
+            for (int j2 = i + 1; j2 < d; ++j2)
+                v *= r.shape[k][j2];
+            a.st[k] = v;
         }
-        if ((km >> i) & 1u) {
-            magic_for((uint32_t)c, &P.kax[dk]);
+        if (na > 0 && ax[na - 1].keep == a.keep) {
+            MAx &b = ax[na - 1];
+            bool ok = true;
+            for (int k = 0; k < n && ok; ++k)
+                ok = b.st[k] == a.c * a.st[k];
+            int64_t mc;
+            if (ok && mul_ok(b.c, a.c, &mc)) {
+                b.c = mc;
+                for (int k = 0; k < n; ++k)
+                    b.st[k] = a.st[k];
+                continue;
+            }
+        }
+        ax[na++] = a;
+    }
+    int dk = 0, dr = 0;
+    uint64_t nout = 1, nred = 1;
+    for (int i = 0; i < na; ++i) {
+        if (ax[i].c >= (int64_t(1) << 32))
+            return TRIOT_E_UNSUPPORTED;
+        if (ax[i].keep) {
+            magic_for((uint32_t)ax[i].c, &P.kax[dk]);
             for (int k = 0; k < n; ++k)
-                P.kstride[k][dk] = st[k];
-            nout *= (uint64_t)c;
+                P.kstride[k][dk] = ax[i].st[k];
+            nout *= (uint64_t)ax[i].c;
             ++dk;
         } else {
-            magic_for((uint32_t)c, &P.rax[dr]);
+            magic_for((uint32_t)ax[i].c, &P.rax[dr]);
             for (int k = 0; k < n; ++k)
-                P.rstride[k][dr] = st[k];
-            nred *= (uint64_t)c;
+                P.rstride[k][dr] = ax[i].st[k];
+            nred *= (uint64_t)ax[i].c;
             ++dr;
         }
     }
     if (nout >= (uint64_t(1) << 32))
         return TRIOT_E_UNSUPPORTED;
+    // the innermost axis is reduced and every operand's last axis
+    bool inner_unit = dr > 0 && na > 0 && !ax[na - 1].keep;
+    for (int k = 0; k < n && inner_unit; ++k)
+        inner_unit = P.rstride[k][dr - 1] == 1;
     const int64_t target = marginal_thread_target(cus);
     uint64_t parts = 1;
-    if ((int64_t)nout < target) {
-        parts = (uint64_t)((target + (int64_t)nout - 1) / (int64_t)nout);
-        // at least 64 reduced tuples per part
-        parts = std::min<uint64_t>(parts, std::max<uint64_t>(1, nred / 64));
+    uint32_t mode = 0, clen = 0;
+    if (inner_unit && dr == 1 && nred >= 1024 && (int64_t)nout * 64 <= target) {
+        // interleaved: chunks of >= 1024 elements, 64 lanes each
+        const uint64_t chunks = std::max<uint64_t>(
+            1, std::min<uint64_t>((nred + 1023) / 1024, (uint64_t)(target / ((int64_t)nout * 64))));
+        clen = (uint32_t)((nred + chunks - 1) / chunks);
+        clen = (clen + 63) / 64 * 64;
+        parts = 64 * ((nred + clen - 1) / clen);
+        mode = 2;
+    } else {
+        const bool vec = inner_unit && (P.rax[dr - 1].c % 4) == 0;
+        const uint64_t units = vec ? nred / 4 : nred;   // parts split whole vectors
+        if ((int64_t)nout < target) {
+            parts = (uint64_t)((target + (int64_t)nout - 1) / (int64_t)nout);
+            // at least 64 reduced tuples per part
+            parts = std::min<uint64_t>(parts, std::max<uint64_t>(1, nred / 64));
+            parts = std::min<uint64_t>(parts, std::max<uint64_t>(1, units));
+        }
+        mode = vec ? 1 : 0;
     }
     P.n = (uint32_t)n;
     P.dk = (uint32_t)dk;
     P.dr = (uint32_t)dr;
     P.parts = (uint32_t)parts;
+    P.mode = mode;
+    P.clen = clen;
     P.nout = nout;
     P.nred = nred;
     for (int k = 0; k < n; ++k) {
         P.base[k] = r.base[k];
         P.ptr[k] = (uint64_t)(uintptr_t)r.ptr[k];
     }
-    (void)cus;
     return TRIOT_OK;
 }
 
