@@ -308,12 +308,13 @@ triot_status triot_schedule_get(triot_op op, int n_tensors, int d, const int64_t
                                 const int64_t *bases, const void *params,
                                 triot_schedule *schedule);
 
-/* Set the launch schedule of a batch (cache policy, blocks per CU, box
- * rows, unit size; vec_max and unit_order are ignored: batch items use
- * 4-byte lanes and contiguous unit ranges).  Releases the planned table
- * and graph: the next triot_apply_batched plans and captures afresh.
- * The default is non-temporal loads and stores, 8 blocks per CU,
- * 8192-element units, 1024 box rows.  TRIOT_E_INVALID for a knob out of range. */
+/* Set the launch schedule of a batch (lane width, cache policy, blocks per
+ * CU, box rows, unit size; a vec_max of 4 lets items take 4-word lanes,
+ * 1 or 2 keeps 1-word lanes; unit_order is ignored: a batch takes
+ * contiguous unit ranges).  Releases the planned table and graph: the next
+ * triot_apply_batched plans and captures afresh.  The default is 4-word
+ * lanes, non-temporal loads and stores, 8 blocks per CU, units of 4096
+ * lanes, 1024 box rows.  TRIOT_E_INVALID for a knob out of range. */
 triot_status triot_batch_set_schedule(triot_batch *handle, const triot_schedule *schedule);
 
 /* ---- diagnostics -------------------------------------------------------- */

@@ -528,20 +528,21 @@ extern "C" triot_status triot_schedule_get(triot_op op, int n_tensors, int d,
 
 // ---- batched form --------------------------------------------------------
 
-// Batch items are planned with 4-byte lanes (one code path for any
-// alignment) and never get the small-problem unit shrink (the batch as a
-// whole fills the device).  Default: non-temporal loads and stores, 8
-// workgroups per CU, 8192-element units (the fastest of cache policy x
-// {2,4,8} workgroups x {2048..16384} elements on 4096 ragged pads, timed
-// cold).
+// Batch items are planned with 4-word lanes where their rows allow (else
+// 1-word lanes; the batched kernel has no 2-word path) and never get the
+// small-problem unit shrink (the batch as a whole fills the device).
+// Default: non-temporal loads and stores, 8 workgroups per CU, units of
+// 4096 lanes (the fastest of cache policy x {2,4,8} workgroups x
+// {2048..16384} lanes on 4096 ragged pads, timed cold).
 static Sched batch_default_sched()
 {
     Sched s;
-    s.vec_max = 1;
-    s.pe_target = 8192;
+    s.vec_max = 4;
+    s.pe_target = 4096;
     s.cache = 1;
     s.blocks_per_cu = 8;
     s.small_units = false;
+    s.no_vec2 = true;
     return s;
 }
 
@@ -599,6 +600,7 @@ extern "C" triot_status triot_batch_set_schedule(triot_batch *handle, const trio
     if (!handle || !schedule)
         return TRIOT_E_INVALID;
     Sched s = batch_default_sched();
+    s.vec_max = schedule->vec_max >= 4 ? 4 : 1;
     s.cache = schedule->cache_policy;
     s.blocks_per_cu = schedule->blocks_per_cu;
     s.rb_max = schedule->box_rows_max;
@@ -709,6 +711,8 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
         triot_status st = plan_coiter(r, s, cus, &L);
         if (st != TRIOT_OK)
             return st;
+        if (L.plan.vec != 1 && L.plan.vec != 4)
+            return TRIOT_E_UNSUPPORTED;   // the batched kernel runs 4- or 1-word lanes
         if (L.plan.RB > 1)
             rows_max = std::max(rows_max, L.plan.RB);
         plans.push_back(L.plan);

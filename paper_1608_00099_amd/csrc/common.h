@@ -70,6 +70,10 @@ struct CoPlan {
     // rows are whole vectors).
     uint32_t tshift;
     uint32_t tskip;
+    // EMBED_FILL with vectors: the source's inner window extent in elements
+    // (NOBOUND = none).  A vector wholly inside it is loaded whole, one
+    // straddling it word by word, and the rest of the vector is zero.
+    uint32_t ibel;
     uint32_t unit;       // 1 when every inner stride is 1
     uint32_t interleave; // unit order: 0 a contiguous range of units per
                          // workgroup, 1 units dealt round-robin

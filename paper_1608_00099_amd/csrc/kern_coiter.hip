@@ -315,12 +315,28 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                 if (valid[u])
                     gstore<VU, CP>(bp[0], off[0][u], v[u]);
         } else if constexpr (OP == CO_FILL) {
+            // Vectors: the source's inner bound is checked per word (ibel);
+            // the destination vector, a ragged row's last included, is
+            // stored whole (shared words get the same value twice).
             VU v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 v[u] = (VU)0u;
-                if (valid[u] && (pm[u] & 2u))
-                    v[u] = gload<VU, CP>(bp[1], off[1][u]);
+                if (valid[u] && (pm[u] & 2u)) {
+                    if constexpr (V == 1) {
+                        v[u] = gload<VU, CP>(bp[1], off[1][u]);
+                    } else {
+                        const uint32_t jel = jj[u] * V - (tl[u] ? P.tskip : 0u);
+                        if (jel + V <= P.ibel) {
+                            v[u] = gload<VU, CP>(bp[1], off[1][u]);
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < V; ++c)
+                                if (jel + (uint32_t)c < P.ibel)
+                                    v[u][c] = gload<uint32_t, CP>(bp[1], off[1][u] + 4u * c);
+                        }
+                    }
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -454,7 +470,9 @@ __global__ __launch_bounds__(NT) void coiter_kernel(const CoPlan P)
 // Batched persistent kernel: one launch over a device table of item plans.
 // Work units of all items are numbered consecutively (ustart holds each
 // item's first unit); every workgroup walks a contiguous range of units and
-// re-tabulates its box rows whenever the range enters a new item.
+// re-tabulates its box rows whenever the range enters a new item.  Each
+// item runs with its own lane width: 4 words (unit-stride rows, ragged or
+// not) or 1.
 // ---------------------------------------------------------------------
 template <int OP, int U, int CP>
 __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ plans,
@@ -503,7 +521,20 @@ __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ 
         const RowTable T{lds_rows, P.RB};
         const bool rows1 = P.RB == 1;
         const uint32_t lu = u - first;
-        if (rows1) {
+        if (P.vec == 4) {
+            // 4-word lanes: unit-stride rows, possibly ragged
+            if (P.tskip) {
+                if (rows1)
+                    run_unit<OP, 4, U, true, true, CP, true>(P, lu, T);
+                else
+                    run_unit<OP, 4, U, false, true, CP, true>(P, lu, T);
+            } else {
+                if (rows1)
+                    run_unit<OP, 4, U, true, true, CP, false>(P, lu, T);
+                else
+                    run_unit<OP, 4, U, false, true, CP, false>(P, lu, T);
+            }
+        } else if (rows1) {
             if (P.unit)
                 run_unit<OP, 1, U, true, true, CP, false>(P, lu, T);
             else
@@ -568,8 +599,8 @@ static hipError_t pick_rows(const CoLaunch &L, hipStream_t st)
 {
     if (L.plan.tskip) {
         // ragged rows: planned only for vectors of unit-stride rows, for
-        // ops without window predicates
-        if constexpr (V > 1 && !OpInfo<OP>::PRED && OP != CO_INDEX) {
+        // ops without window predicates and EMBED_FILL
+        if constexpr (V > 1 && (!OpInfo<OP>::PRED || OP == CO_FILL) && OP != CO_INDEX) {
             if (!L.unit)
                 return hipErrorInvalidValue;
             return L.rows1 ? go<OP, V, U, true, true, CP, true>(L, st)

@@ -478,20 +478,26 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     //    writes every operand on the whole counter (no window predicates):
     //    each row's last vector is moved back to end at the row end, reads
     //    words of the vector before it again and stores only its new words.
+    //    EMBED_FILL also takes ragged rows (its destination is the counter,
+    //    stored whole like COPY's) and a source inner bound at any element:
+    //    the kernel loads a vector that straddles it word by word.
     const Ax &in = m[D - 1];
+    const bool fill_el = r.op == TRIOT_OP_EMBED_FILL && in.c < (int64_t(1) << 31);
     const bool ragged_ok = r.op == TRIOT_OP_COPY || r.op == TRIOT_OP_MUL_ACC ||
-                           r.op == TRIOT_OP_MUL || r.op == TRIOT_OP_XPYX_MZ;
+                           r.op == TRIOT_OP_MUL || r.op == TRIOT_OP_XPYX_MZ || fill_el;
     int vec = 1;
     int64_t rtail = 0;   // words in a row's last vector (0: whole vectors)
     if (r.op != TRIOT_OP_INDEX) {
         for (int v = std::min(4, std::max(1, s.vec_max)); v > 1; v >>= 1) {
+            if (v == 2 && s.no_vec2)
+                continue;
             const bool whole = (in.c % v) == 0 && in.c / v >= 2;
             const bool rag = !whole && ragged_ok && in.c > v;
             bool ok = whole || rag;
             for (int k = 0; k < n && ok; ++k) {
                 if (in.S[k] != 1 || ((uintptr_t)r.ptr[k] % 4) != 0)
                     ok = false;
-                if (in.B[k] != -1 && (rag || in.B[k] % v != 0))
+                if (in.B[k] != -1 && !fill_el && (rag || in.B[k] % v != 0))
                     ok = false;
             }
             if (ok) {
@@ -706,9 +712,15 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
                 below *= kx[i].c;
         }
     }
+    P.ibel = NOBOUND;
     for (int k = 0; k < n; ++k) {
         P.istride[k] = (uint32_t)is[k];
-        if (in.B[k] >= 0) {
+        if (in.B[k] >= 0 && fill_el && vec > 1) {
+            // element-precise source bound (k == 1, the only bounded operand)
+            P.ibound[k] = NOBOUND;
+            P.ibel = (uint32_t)in.B[k];
+            predmask |= 1u << k;
+        } else if (in.B[k] >= 0) {
             P.ibound[k] = (uint32_t)(in.B[k] / vec);
             predmask |= 1u << k;
         } else {

@@ -19,6 +19,7 @@ struct Sched {
     int blocks_per_cu = 4;  // persistent workgroups per CU
     int order = 0;          // unit order: 0 blocked ranges, 1 round-robin
     bool small_units = true;  // shrink units of small problems (not for batch items)
+    bool no_vec2 = false;     // lanes of 4 or 1 words only (the batched kernel)
     int rb_max = RB_MAX;    // rows per box (LDS table) upper bound
     int pe_target = 8192;   // elements per work unit
 };

@@ -160,9 +160,12 @@ def test_plan_ragged_rows():
     # whole vectors report no tail
     p = api.describe(L.OP_MUL_ACC, [(5, 40), (5, 44), (5, 48)])
     assert p["vec"] == 4 and p["row_tail"] == 0
-    # the predicated ops (window bounds inside the counter) keep 1-word
-    # lanes on ragged rows, as does a row of at most one vector
+    # EMBED_FILL: ragged destination rows and a source bound at any word
     p = api.describe(L.OP_EMBED_FILL, [(9, 11), (7, 9)], params=L.CopyParams(4))
+    assert p["vec"] == 4 and p["row_tail"] == 3
+    # the adjoint product (window predicates on several operands) keeps
+    # 1-word lanes on ragged rows, as does a row of at most one vector
+    p = api.describe(L.OP_MUL_ADJ, [(6, 9), (6, 7), (6, 7), (6, 9), (6, 7)])
     assert p["vec"] == 1 and p["row_tail"] == 0
     p = api.describe(L.OP_MUL_ACC, [(5, 2), (5, 3), (5, 3)])
     assert p["vec"] == 1 and p["row_tail"] == 0

@@ -150,3 +150,42 @@ def test_batched_schedule_rejects_out_of_range():
             b.set_schedule(**kw)
         assert e.value.status == L.E_INVALID
     b.close()
+
+
+def test_batched_lane_widths_agree():
+    """Items with 4-word lanes (the default) and with 1-word lanes give the
+    oracle's bits, EMBED_FILL and MUL_ACC."""
+    announce("batched lane widths")
+    shapes = inputs.cfg4_shapes()[300:700]
+    xs_np = inputs.cfg4_values(shapes)
+    xs = [torch.from_numpy(x).cuda() for x in xs_np]
+    for vec in (4, 1):
+        dsts = [torch.full(inputs.padded_shape(sx, sy), 7.0, device="cuda") for sx, sy in shapes]
+        b = api.Batch()
+        b.set_schedule(vec_max=vec)
+        b.apply(L.OP_EMBED_FILL, [[d_, x] for d_, x in zip(dsts, xs)])
+        torch.cuda.synchronize()
+        _check_items(dsts, xs_np, shapes)
+        b.close()
+    rng = np.random.default_rng(31)
+    for vec in (4, 1):
+        b = api.Batch()
+        b.set_schedule(vec_max=vec)
+        items, want = [], []
+        for k in range(40):
+            d = 1 + k % 4
+            x_s = tuple(int(v) for v in rng.integers(3, 40, size=d))
+            y_s = tuple(s + int(rng.integers(0, 3)) for s in x_s)
+            x = rng.standard_normal(x_s).astype(np.float32)
+            y = rng.standard_normal(y_s).astype(np.float32)
+            z = rng.standard_normal(y_s).astype(np.float32)
+            w = x.copy()
+            oracle.mul_acc(x_s, w.reshape(-1), x_s, y.reshape(-1), y_s, z.reshape(-1), y_s)
+            items.append([torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(),
+                          torch.from_numpy(z).cuda()])
+            want.append(w)
+        b.apply(L.OP_MUL_ACC, items)
+        torch.cuda.synchronize()
+        for it, w in zip(items, want):
+            assert it[0].cpu().numpy().tobytes() == w.tobytes()
+        b.close()

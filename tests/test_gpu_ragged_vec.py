@@ -151,3 +151,45 @@ def test_ragged_mul_and_xpyx_mz(case, sched):
     _pin(L.OP_XPYX_MZ, [gx, ga, gz], [counter, big, big], counter, sched)
     api.xpyx_mz_(gx, ga, gz, counter=counter)
     assert bits_equal(host(gx), want), first_mismatch(host(gx), want)
+
+
+# EMBED_FILL over a destination counter: (dst shape, src shape, src base
+# shift).  Ragged destination rows and source inner bounds at every
+# residue mod 4, so vectors lie wholly inside, straddle or lie past the
+# source window.
+FILL_CASES = [
+    ((9, 11), (7, 9), 0),
+    ((13, 6), (13, 5), 0),
+    ((5, 7, 23), (4, 7, 21), 0),
+    ((6, 5, 4, 39), (3, 5, 4, 17), 0),
+    ((3, 1030), (3, 1027), 0),
+    ((2, 8, 16), (2, 8, 13), 0),
+    ((40, 41), (40, 38), 1),
+    ((100003,), (99998,), 2),
+]
+
+
+@pytest.mark.parametrize("vec", [4, 2, 1])
+@pytest.mark.parametrize("case", range(len(FILL_CASES)))
+def test_embed_fill_vectors_with_ragged_rows_and_bounds(case, vec):
+    dst_s, src_s, shift = FILL_CASES[case]
+    announce("fill vectors", dst_s, src_s, shift, vec)
+    rng = np.random.default_rng(900 + case)
+    # the source window: src_s inside a parent grown by `shift` on the last axis
+    parent = tuple(src_s[:-1]) + (src_s[-1] + shift,)
+    x = rng.standard_normal(parent).astype(np.float32)
+    want = np.full(dst_s, 7.0, dtype=np.float32)
+    oracle.embed_fill(dst_s, want.reshape(-1), dst_s, x.reshape(-1), parent, 0, shift)
+    g = torch.full(dst_s, 7.0, dtype=torch.float32, device="cuda")
+    gx = dev(x)
+    shapes = [dst_s, parent]
+    api.schedule_set(L.OP_EMBED_FILL, [g, gx], shapes=shapes, counter=dst_s, bases=[0, shift],
+                     params=L.CopyParams(4), vec_max=vec, cache_policy=1, blocks_per_cu=4,
+                     box_rows_max=1024, unit_elems=8192, unit_order=0)
+    plan = api.describe(L.OP_EMBED_FILL, shapes, counter=dst_s, ptrs=[g.data_ptr(), gx.data_ptr()],
+                        bases=[0, shift], params=L.CopyParams(4))
+    if vec == 4 and dst_s[-1] > 4:
+        assert plan["vec"] == 4
+    api.apply(L.OP_EMBED_FILL, [g, gx], shapes, dst_s, [0, shift], L.CopyParams(4),
+              what="embed_fill")
+    assert bits_equal(host(g), want), first_mismatch(host(g), want)
