@@ -551,6 +551,10 @@ def _cfg5(dev, out):
     lam = torch.from_numpy(lam_np.astype(np.float32)).to(dev)
 
     def fwd_bwd():
+        # a fresh step: gradients set to None, as optimizers' zero_grad does,
+        # so backward writes them instead of adding a second full pass
+        x.grad = None
+        w.grad = None
         P = autograd.pad_embed(x, inputs.CFG5_P)
         y = autograd.mul(P, w)
         M, E, C = autograd.moments(y)

@@ -276,6 +276,45 @@ __global__ __launch_bounds__(CONV_NT) void conv_kernel_rows(const ConvPlan P)
     int32_t lrow = (int32_t)(lo0 * ls1 + lo1);
     int32_t rrow = (int32_t)((v0 - lo0) * rs1 + (v1 - lo1));
     double acc = 0.0;
+    if (ls1 <= 8) {
+        // Rows of at most 8 terms: one chunk per row, and the next row's
+        // words are read from LDS before this row's terms are added (two
+        // buffers in turn), so LDS latency overlaps the add chain.
+        double a0[8], b0[8], a1[8], b1[8];
+        auto ld = [&](double (&a)[8], double (&b)[8], int32_t lr, int32_t rr) {
+            const double *lp = Ls + lr;
+            const double *rp = Rs + rr;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                a[u] = lp[u];
+                b[u] = rp[-u];
+            }
+        };
+        auto add = [&](const double (&a)[8], const double (&b)[8]) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if ((uint32_t)u < n1) {
+                    const double prod = a[u] * b[u];
+                    acc = acc + prod;
+                }
+            }
+        };
+        ld(a0, b0, lrow, rrow);
+        uint32_t j = 0;
+        for (; j + 2 <= n0; j += 2) {
+            ld(a1, b1, lrow + (int32_t)ls1, rrow - (int32_t)rs1);
+            add(a0, b0);
+            lrow += 2 * (int32_t)ls1;
+            rrow -= 2 * (int32_t)rs1;
+            if (j + 2 < n0)
+                ld(a0, b0, lrow, rrow);
+            add(a1, b1);
+        }
+        if (j < n0)
+            add(a0, b0);
+        ((GLOBAL double *)(uintptr_t)P.out)[f] = acc;
+        return;
+    }
     for (uint32_t j = 0; j < n0; ++j) {
         const double *lp = Ls + lrow;
         const double *rp = Rs + rrow;
