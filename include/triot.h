@@ -162,9 +162,14 @@ typedef struct triot_copy_params {
 
 #define TRIOT_MOMENTS_FIRST 1  /* M and E (always produced) */
 #define TRIOT_MOMENTS_COV 2    /* add the covariance upper triangle */
+/* A load hint, no effect on results: the operands were just written (by
+ * the previous kernel of a pipeline) and may still sit in the caches, so
+ * load them through the caches rather than streaming past them (the
+ * default, faster for data that is not cached). */
+#define TRIOT_MOMENTS_CACHED 4
 
 typedef struct triot_moments_params {
-    int flags;               /* TRIOT_MOMENTS_FIRST [| TRIOT_MOMENTS_COV] */
+    int flags;               /* TRIOT_MOMENTS_FIRST [| TRIOT_MOMENTS_COV] [| TRIOT_MOMENTS_CACHED] */
     double *out64;           /* optional device buffer: the same layout in float64 */
 } triot_moments_params;
 

@@ -26,6 +26,7 @@ STATUS_NAMES = ["OK", "E_INVALID", "E_DIM", "E_BOUNDS", "E_ALIAS", "E_OVERFLOW",
 
 MOMENTS_FIRST = 1
 MOMENTS_COV = 2
+MOMENTS_CACHED = 4   # load hint: the operands were just written
 
 
 class CopyParams(ctypes.Structure):

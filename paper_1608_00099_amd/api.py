@@ -177,9 +177,11 @@ def n_moments(d: int, cov: bool) -> int:
     return 1 + d + (d * (d + 1) // 2 if cov else 0)
 
 
-def moments(p, cov=True, others=(), counter=None):
+def moments(p, cov=True, others=(), counter=None, cached=False):
     """(out32, out64): [M, E_0..E_{d-1}(, upper-triangle C)] of the weights
-    w(t) = p[t] * prod(others[k][t]) over counter (default: intersection)."""
+    w(t) = p[t] * prod(others[k][t]) over counter (default: intersection).
+    cached: a load hint for operands the previous kernel just wrote (no
+    effect on the results)."""
     tensors = [p] + list(others)
     _f32(*tensors)
     dev, shapes = _prep(tensors, None)
@@ -188,7 +190,8 @@ def moments(p, cov=True, others=(), counter=None):
     out32 = torch.empty(nout, dtype=torch.float32, device=dev)
     out64 = torch.empty(nout, dtype=torch.float64, device=dev)
     ws = workspace_for(L.OP_MOMENTS, shapes, counter, dev)
-    params = L.MomentsParams(L.MOMENTS_FIRST | (L.MOMENTS_COV if cov else 0), out64.data_ptr())
+    flags = L.MOMENTS_FIRST | (L.MOMENTS_COV if cov else 0) | (L.MOMENTS_CACHED if cached else 0)
+    params = L.MomentsParams(flags, out64.data_ptr())
     apply(L.OP_MOMENTS, tensors, shapes, counter, None, params, out=out32, workspace=ws,
           what="moments")
     return out32, out64

@@ -42,12 +42,14 @@ class Mul(torch.autograd.Function):
 
 
 class Moments(torch.autograd.Function):
-    """Returns (M, E, C); C is empty unless cov=True (upper triangle)."""
+    """Returns (M, E, C); C is empty unless cov=True (upper triangle).  In a
+    pipeline the weights are the previous op's output, so they are loaded
+    through the caches (a hint; the results do not depend on it)."""
 
     @staticmethod
     def forward(ctx, p, cov):
         p = p.contiguous()
-        out32, out64 = api.moments(p, cov=cov)
+        out32, out64 = api.moments(p, cov=cov, cached=True)
         d = p.dim()
         ctx.cov = bool(cov)
         ctx.shape = tuple(p.shape)

@@ -276,8 +276,9 @@ __device__ __forceinline__ void seg_load_half(const SegPlan &P, const int64_t of
     }
 }
 
-// Folds one segment whose first half w0 is already loaded (the second half,
-// when len > HALF, is loaded here).
+// Folds one segment whose first half w0 is already loaded.  The second
+// half, when len > HALF, is loaded here before the first half is summed, so
+// both halves' loads are in flight together.
 // ORDER: 0 the mass only, 1 with the first sum, 2 with the second too.
 template <bool VEC, bool NTL, bool MULTI, int ORDER>
 __device__ __forceinline__ void seg_moments(const SegPlan &P, const int64_t off[4], uint32_t len,
@@ -286,13 +287,13 @@ __device__ __forceinline__ void seg_moments(const SegPlan &P, const int64_t off[
 {
     constexpr bool SECOND = ORDER >= 2;
     double A = 0.0, B = 0.0, C = 0.0;
+    HalfW<MULTI> w1;
+    if (len > (uint32_t)HALF)
+        seg_load_half<VEC, NTL, MULTI>(P, off, len, HALF, w1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const uint32_t h0 = (uint32_t)(h * HALF);
         if (h == 0 || len > h0) {
-            HalfW<MULTI> w1;
-            if (h == 1)
-                seg_load_half<VEC, NTL, MULTI>(P, off, len, h0, w1);
 #pragma unroll
             for (int j = 0; j < HALF; ++j) {
                 if (h0 + (uint32_t)j < len) {
@@ -345,12 +346,12 @@ __device__ __forceinline__ void seg_offsets(const SegPlan &P, const Seg &sg, int
 // order) into one partial per term, written term-major to the workspace.
 // DM: accumulator positions (the exact number of kept axes for the
 // covariance tier; 8 or 32 for first moments only).
-// Resident workgroups per CU the register allocation aims at: 4 (128
-// VGPRs) while the accumulators leave room for the segment's 32 loaded
-// words, else 2.
+// Resident workgroups per CU the register allocation aims at: 2, the
+// number the pass runs (room for both halves of a segment in flight beside
+// the accumulators).
 template <int DM, bool COV, bool MULTI> constexpr int moments_min_blocks()
 {
-    return (!MULTI && (COV ? 1 + DM + DM * (DM + 1) / 2 : 1 + DM) <= 28) ? 4 : 2;
+    return 2;
 }
 
 template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true>
@@ -939,20 +940,17 @@ template <int DM, bool COV>
 static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
 {
     const bool multi = L.plan.n > 1;
-    if (L.plan.vec4) {
-        if (multi)
-            hipLaunchKernelGGL((moments_kernel<DM, COV, true, true>), dim3(L.blocks), dim3(NT), 0, st,
-                               L.plan);
-        else
-            hipLaunchKernelGGL((moments_kernel<DM, COV, true, false>), dim3(L.blocks), dim3(NT), 0,
-                               st, L.plan);
-    } else {
-        if (multi)
-            hipLaunchKernelGGL((moments_kernel<DM, COV, false, true>), dim3(L.blocks), dim3(NT), 0,
-                               st, L.plan);
-        else
-            hipLaunchKernelGGL((moments_kernel<DM, COV, false, false>), dim3(L.blocks), dim3(NT), 0,
-                               st, L.plan);
+    const bool cached = (L.plan.flags & TRIOT_MOMENTS_CACHED) != 0;
+    const int k = (L.plan.vec4 ? 4 : 0) + (multi ? 2 : 0) + (cached ? 1 : 0);
+    switch (k) {
+    case 7: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+    case 6: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+    case 5: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+    case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+    case 3: hipLaunchKernelGGL((moments_kernel<DM, COV, false, true, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+    case 2: hipLaunchKernelGGL((moments_kernel<DM, COV, false, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+    case 1: hipLaunchKernelGGL((moments_kernel<DM, COV, false, false, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+    default: hipLaunchKernelGGL((moments_kernel<DM, COV, false, false, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
     }
     hipLaunchKernelGGL((moments_final_kernel<DM, COV>), dim3(1), dim3(FNT), 0, st, L.plan);
     return hipGetLastError();

@@ -168,7 +168,7 @@ triot_status validate(triot_op op, int n, int d, const int64_t *shapes, const in
     } else if (op == TRIOT_OP_MOMENTS) {
         if (params) {
             int f = ((const triot_moments_params *)params)->flags;
-            if (f & ~(TRIOT_MOMENTS_FIRST | TRIOT_MOMENTS_COV))
+            if (f & ~(TRIOT_MOMENTS_FIRST | TRIOT_MOMENTS_COV | TRIOT_MOMENTS_CACHED))
                 return TRIOT_E_INVALID;
         }
     } else if (op == TRIOT_OP_MOMENTS_ADJ) {

@@ -95,3 +95,40 @@ def test_autograd_functions_match_raw_kernels():
     gm = torch.cat([torch.zeros(1, device="cuda"), gE, gC])
     g = api.moments_adj(p.shape, o64, gm, cov=True)
     assert torch.allclose(p.grad, g, rtol=1e-6, atol=0)
+
+
+def test_pipeline_in_captured_graphs_matches_eager():
+    """Forward and backward of the pipeline captured as graphs
+    (torch.cuda.make_graphed_callables over the library's Functions) and
+    replayed, with eager work and synchronisation between replays: every
+    replay gives the eager loss and gradients bit for bit."""
+    announce("autograd cfg5 graphed")
+    x_np, w_np, lam = inputs.cfg5_values()
+    lam_t = torch.from_numpy(lam.astype(np.float32)).cuda()
+
+    def step(x, w):
+        P = autograd.pad_embed(x, inputs.CFG5_P)
+        y = autograd.mul(P, w)
+        M, E, C = autograd.moments(y)
+        return (lam_t * E).sum()
+
+    x = torch.from_numpy(x_np).cuda().requires_grad_(True)
+    w = torch.from_numpy(w_np).cuda().requires_grad_(True)
+    loss = step(x, w)
+    loss.backward()
+    torch.cuda.synchronize()
+    ref = (loss.detach().cpu().numpy(), x.grad.cpu().numpy(), w.grad.cpu().numpy())
+    xg = x.detach().clone().requires_grad_(True)
+    wg = w.detach().clone().requires_grad_(True)
+    g_step = torch.cuda.make_graphed_callables(step, (xg, wg))
+    for rep in range(3):
+        xg.grad = None
+        wg.grad = None
+        other = torch.arange(4096, device="cuda", dtype=torch.float32)
+        assert float(other.sum()) == 4096 * 4095 / 2           # eager work, synchronised
+        loss = g_step(xg, wg)
+        loss.backward()
+        torch.cuda.synchronize()
+        got = (loss.detach().cpu().numpy(), xg.grad.cpu().numpy(), wg.grad.cpu().numpy())
+        for a, b in zip(got, ref):
+            assert a.tobytes() == b.tobytes(), rep

@@ -342,6 +342,9 @@ def test_moments_shapes(shape, cov):
     want = oracle.moments(shape, [p.reshape(-1)], [shape], cov=cov)
     o32, o64 = api.moments(dev(p), cov=cov)
     _check_moments(host(o32), host(o64), want, len(shape), cov)
+    # the cached-load hint changes how the operand is loaded, not the sums
+    c32, c64 = api.moments(dev(p), cov=cov, cached=True)
+    assert bits_equal(host(c32), host(o32)) and bits_equal(host(c64), host(o64))
 
 
 def test_moments_invariants_on_gpu():
