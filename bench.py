@@ -17,8 +17,9 @@ workload, and per-configuration figures for the other parts of the hot path
 the small pad-embed) next to a plain device-copy ceiling.
 
 The sweep's launch schedules are pinned from a JSON file written by an
-earlier `--retune --save-schedules` run on an MI355X (the library's
-autotuner per launch, then the in-sequence refinement of tune.py), so that
+earlier `--retune --save-schedules` run on an MI355X (a grid of schedules
+ranked alone for every launch, then the in-sequence refinement of tune.py),
+so that
 every run and its profiles launch the same kernels; `--retune` tunes afresh.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
@@ -130,10 +131,24 @@ def problems_of(launches):
     return out
 
 
-def sequence_tune(launches):
-    """Refine the schedules in the sequence they run in (see tune.py)."""
-    from paper_1608_00099_amd import tune
-    tune.tune_sequence(problems_of(launches), [x[2] for x in launches], log=log)
+def sequence_tune(launches, dev):
+    """Rank a grid of schedules for every launch alone (cold), pin each
+    launch's fastest, then refine in the sequence they run in, trying each
+    launch's six fastest first (see tune.py)."""
+    import torch
+    from paper_1608_00099_amd import api, tune
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+    probs = problems_of(launches)
+    cands = []
+    for (name, op, fn, nbytes, it), p in zip(launches, probs):
+        ranked = tune.rank_alone(p, fn, flush=flush)
+        api.schedule_set(p["op"], p["tensors"], counter=p.get("counter"), params=p.get("params"),
+                         **ranked[0][1])
+        cands.append([sched for _, sched in ranked[:6]])
+        log("ranked %d schedules for %s alone: best %.1f us" % (len(ranked), name,
+                                                                ranked[0][0] * 1e3))
+    del flush
+    tune.tune_sequence(probs, [x[2] for x in launches], log=log, candidates=cands)
 
 
 def save_schedules(launches, path):
@@ -637,7 +652,7 @@ def main():
                     help="ignore --schedules: run the autotuner on every launch, then refine "
                          "the schedules in sequence")
     ap.add_argument("--no-seq-tune", action="store_true",
-                    help="with --retune: skip the in-sequence refinement")
+                    help="with --retune: the library's autotuner per launch only")
     ap.add_argument("--save-schedules", default=None,
                     help="write the schedules the sweep ran with to this JSON file")
     ap.add_argument("--no-tune", action="store_true",
@@ -666,13 +681,14 @@ def main():
     if args.no_tune:
         how = "library defaults"
     elif args.retune or not os.path.exists(args.schedules):
-        log("autotuning the %d launch schedules" % len(launches))
-        autotune_all(launches)
-        how = "autotuned per launch"
-        if not args.no_seq_tune:
-            log("refining the schedules in sequence")
-            sequence_tune(launches)
-            how += ", refined in sequence"
+        if args.no_seq_tune:
+            log("autotuning the %d launch schedules" % len(launches))
+            autotune_all(launches)
+            how = "autotuned per launch"
+        else:
+            log("ranking schedules alone, then refining them in sequence")
+            sequence_tune(launches, dev)
+            how = "ranked alone over a grid, refined in sequence"
     else:
         pin_schedules(launches, args.schedules)
         how = "pinned from %s" % os.path.relpath(args.schedules, ROOT)
