@@ -692,7 +692,7 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
         return to_status(hipGraphLaunch(handle->exec, stream));
     }
 
-    // Plan every item (4-byte lanes keep one code path for any alignment).
+    // Plan every item with the batch's schedule (4- or 1-word lanes).
     batch_release(handle);
     handle->replayed = 0;
     const Sched s = handle->sched;
