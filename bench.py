@@ -728,6 +728,15 @@ def main():
                 "traffic": traffic, "kernel": dom, "launches_per_step": dk["launches"],
                 "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": int(avg_bytes)}
 
+    # The pad-embed destinations are zeroed once, at allocation; a zero
+    # fill of all seven (torch's fill kernel) is timed on its own line, not
+    # folded into the step.
+    zbytes = sum(4 * it["dst"].numel() for it in sw.items)
+    tz = event_ms(lambda: [it["dst"].zero_() for it in sw.items], reps=5)
+    zero_fill = {"ms": round(tz["median_ms"], 4), "bytes": zbytes,
+                 "GBs": round(zbytes / tz["median_ms"] / 1e6, 1),
+                 "what": "zero fill of the seven pad-embed destinations, not part of the step"}
+
     cpu = None
     if not args.no_cpu:
         threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
@@ -761,6 +770,7 @@ def main():
                    "wall_ms_per_step": round(wall_ms, 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "dst_zero_fill": zero_fill,
         "per_op": per_op,
         "tuned": tuned,
         "schedules": how,

@@ -240,3 +240,32 @@ def test_schedule_get_reports_defaults_and_pins():
     with pytest.raises(L.TriotError) as e:
         api.schedule_get(L.OP_MOMENTS, [x], params=L.MomentsParams(0, 0))
     assert e.value.status == L.E_UNSUPPORTED
+
+
+def test_rank_alone_and_seeded_sequence_tuning():
+    """rank_alone times a grid for one problem and restores its schedule;
+    tune_sequence seeded with candidates pins one schedule per problem and
+    the results keep the oracle's bits."""
+    from paper_1608_00099_amd import tune
+    announce("rank alone")
+    xs, ys, zs = (40, 37), (41, 39), (40, 38)
+    rng = np.random.default_rng(170)
+    x = rng.standard_normal(xs).astype(np.float32)
+    y = rng.standard_normal(ys).astype(np.float32)
+    z = rng.standard_normal(zs).astype(np.float32)
+    gx, gy, gz = dev(x), dev(y), dev(z)
+    prob = dict(op=L.OP_MUL_ACC, tensors=[gx, gy, gz])
+    before = api.schedule_get(L.OP_MUL_ACC, [gx, gy, gz])
+    grid = dict(vec_max=(4, 1), cache_policy=(0, 1), blocks_per_cu=(1, 4))
+    ranked = tune.rank_alone(prob, lambda: api.mul_acc_(gx, gy, gz), grid=grid, reps=3)
+    assert len(ranked) == 8
+    assert [t for t, _ in ranked] == sorted(t for t, _ in ranked)
+    assert api.schedule_get(L.OP_MUL_ACC, [gx, gy, gz]) == before
+    scheds = tune.tune_sequence([prob], [lambda: api.mul_acc_(gx, gy, gz)], steps=3,
+                                knobs=(), passes=1, candidates=[[s for _, s in ranked[:3]]])
+    assert scheds[0] in [before] + [s for _, s in ranked[:3]]
+    gx.copy_(dev(x))
+    api.mul_acc_(gx, gy, gz)
+    want = x.copy()
+    oracle.mul_acc(xs, want.reshape(-1), xs, y.reshape(-1), ys, z.reshape(-1), zs)
+    assert bits_equal(host(gx), want), first_mismatch(host(gx), want)
