@@ -134,21 +134,21 @@ def problems_of(launches):
 def sequence_tune(launches, dev):
     """Rank a grid of schedules for every launch alone (cold), pin each
     launch's fastest, then refine in the sequence they run in, trying each
-    launch's six fastest first (see tune.py)."""
+    launch's twelve fastest first (three passes; see tune.py)."""
     import torch
     from paper_1608_00099_amd import api, tune
     flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
     probs = problems_of(launches)
     cands = []
     for (name, op, fn, nbytes, it), p in zip(launches, probs):
-        ranked = tune.rank_alone(p, fn, flush=flush)
+        ranked = tune.rank_alone(p, fn, reps=3, flush=flush)
         api.schedule_set(p["op"], p["tensors"], counter=p.get("counter"), params=p.get("params"),
                          **ranked[0][1])
-        cands.append([sched for _, sched in ranked[:6]])
+        cands.append([sched for _, sched in ranked[:12]])
         log("ranked %d schedules for %s alone: best %.1f us" % (len(ranked), name,
                                                                 ranked[0][0] * 1e3))
     del flush
-    tune.tune_sequence(probs, [x[2] for x in launches], log=log, candidates=cands)
+    tune.tune_sequence(probs, [x[2] for x in launches], log=log, candidates=cands, passes=3)
 
 
 def save_schedules(launches, path):

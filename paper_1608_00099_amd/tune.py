@@ -24,8 +24,9 @@ from . import api
 KNOBS = (("vec_max", (4, 2, 1)), ("cache_policy", (0, 1, 2)), ("blocks_per_cu", (1, 2, 4, 8)))
 
 # The full grid ranked alone (cold) before the in-sequence refinement.
-GRID = dict(vec_max=(4, 2, 1), cache_policy=(0, 1, 2), blocks_per_cu=(1, 2, 4, 8),
-            unit_order=(0, 1), box_rows_max=(64, 1024), unit_elems=(4096, 8192, 16384))
+GRID = dict(vec_max=(4, 2, 1), cache_policy=(0, 1, 2), blocks_per_cu=(1, 2, 4, 8, 16),
+            unit_order=(0, 1), box_rows_max=(64, 1024),
+            unit_elems=(2048, 4096, 8192, 16384, 32768))
 
 
 def _key(p):
