@@ -240,7 +240,8 @@ void triot_batch_destroy(triot_batch *handle);
  * the table and captures the launch in a hipGraph; later calls with the
  * same shapes, pointers and op replay the graph on `stream`; a different
  * batch re-plans.  Supported ops: COPY, EMBED_FILL, MUL_ACC, MUL.
- * params as in triot_apply (shared by all items). */
+ * params as in triot_apply (shared by all items).  TRIOT_E_UNSUPPORTED
+ * when the work units of all items reach 2^31. */
 triot_status triot_apply_batched(triot_op op, int n_items, const triot_item *items,
                                  const void *params, triot_batch *handle, hipStream_t stream);
 
@@ -314,12 +315,14 @@ triot_status triot_schedule_get(triot_op op, int n_tensors, int d, const int64_t
                                 triot_schedule *schedule);
 
 /* Set the launch schedule of a batch (lane width, cache policy, blocks per
- * CU, box rows, unit size; a vec_max of 4 lets items take 4-word lanes,
- * 1 or 2 keeps 1-word lanes; unit_order is ignored: a batch takes
- * contiguous unit ranges).  Releases the planned table and graph: the next
+ * CU, box rows, unit size, unit order; a vec_max of 4 lets items take
+ * 4-word lanes, 1 or 2 keeps 1-word lanes; unit_order 0 gives each
+ * workgroup a contiguous range of the work units of all items, 1 deals
+ * them round-robin).  Releases the planned table and graph: the next
  * triot_apply_batched plans and captures afresh.  The default is 4-word
  * lanes, non-temporal loads and stores, 8 blocks per CU, units of 4096
- * lanes, 1024 box rows.  TRIOT_E_INVALID for a knob out of range. */
+ * lanes, 1024 box rows, round-robin units.  TRIOT_E_INVALID for a knob out
+ * of range. */
 triot_status triot_batch_set_schedule(triot_batch *handle, const triot_schedule *schedule);
 
 /* ---- diagnostics -------------------------------------------------------- */

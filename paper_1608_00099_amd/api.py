@@ -340,10 +340,11 @@ class Batch:
         _check(st, "apply_batched")
 
     def set_schedule(self, cache_policy=1, blocks_per_cu=8, box_rows_max=1024, unit_elems=4096,
-                     vec_max=4):
+                     vec_max=4, unit_order=1):
         """Set the launch schedule of this batch (the next apply re-plans and
         re-captures); the defaults are the library's."""
-        sch = L.Schedule(vec_max, cache_policy, blocks_per_cu, box_rows_max, unit_elems, 0)
+        sch = L.Schedule(vec_max, cache_policy, blocks_per_cu, box_rows_max, unit_elems,
+                         unit_order)
         _check(L.triot_batch_set_schedule(self._h, sch), "batch_set_schedule")
 
     def launch(self, device=None):

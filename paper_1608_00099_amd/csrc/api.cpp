@@ -543,6 +543,7 @@ static Sched batch_default_sched()
     s.blocks_per_cu = 8;
     s.small_units = false;
     s.no_vec2 = true;
+    s.order = 1;
     return s;
 }
 
@@ -605,7 +606,7 @@ extern "C" triot_status triot_batch_set_schedule(triot_batch *handle, const trio
     s.blocks_per_cu = schedule->blocks_per_cu;
     s.rb_max = schedule->box_rows_max;
     s.pe_target = schedule->unit_elems;
-    s.order = 0;
+    s.order = schedule->unit_order;
     if (!sched_valid(s))
         return TRIOT_E_INVALID;
     handle->sched = s;
@@ -717,7 +718,7 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
             rows_max = std::max(rows_max, L.plan.RB);
         plans.push_back(L.plan);
         total += L.plan.nunits;
-        if (total >= (uint64_t(1) << 32))
+        if (total >= (uint64_t(1) << 31))
             return TRIOT_E_UNSUPPORTED;
         ustart.push_back((uint32_t)total);
     }
@@ -767,6 +768,7 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
     B.blocks = blocks;
     B.cus = cus;
     B.cache = s.cache;
+    B.rr = s.order ? 1u : 0u;
     B.launched = blocks;
     hipError_t le = launch_batched(co_op_of(op), B, handle->cap);
     handle->blocks = B.launched;

@@ -240,11 +240,16 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
     const uint32_t e1 = min(e0 + P.PE, bev);
     if (e0 >= e1)
         return;
+    // Single-row boxes: the base moves to the vector before the unit's
+    // first (the row start for the first unit), so that the per-lane
+    // offsets stay non-negative for a ragged row's last vector, moved back
+    // by up to V - 1 words, when it is the first vector of a unit.
+    const uint32_t eb = (ROWS1 && e0 >= 1u) ? e0 - 1u : 0u;
     if (ROWS1) {
 #pragma unroll
         for (int k = 0; k < N; ++k)
             if (k < (int)n)
-                bb[k] += (int64_t)e0 * P.istride[k] * V;
+                bb[k] += (int64_t)eb * P.istride[k] * V;
     }
     constexpr uint32_t esz = 4u * V;   // == P.esz: the launcher picks V = P.vec
     gchar *bp[N];
@@ -295,7 +300,7 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
             for (int k = 0; k < N; ++k) {
                 if (k < (int)n) {
                     uint32_t rel = ROWS1 ? 0u : T.off(k, row);
-                    uint32_t xe = ROWS1 ? (x - e0) : x;
+                    uint32_t xe = ROWS1 ? (x - eb) : x;
                     off[k][u] = rel + xe * isb[k] - (tl[u] ? P.tshift : 0u);
                 }
             }
@@ -469,43 +474,48 @@ __global__ __launch_bounds__(NT) void coiter_kernel(const CoPlan P)
 // ---------------------------------------------------------------------
 // Batched persistent kernel: one launch over a device table of item plans.
 // Work units of all items are numbered consecutively (ustart holds each
-// item's first unit); every workgroup walks a contiguous range of units and
-// re-tabulates its box rows whenever the range enters a new item.  Each
-// item runs with its own lane width: 4 words (unit-stride rows, ragged or
-// not) or 1.
+// item's first unit).  Every workgroup walks either a contiguous range of
+// units (rr == 0) or every g-th unit from its own (rr == 1: at any moment
+// the grid sweeps one window of memory), and re-tabulates its box rows
+// whenever it enters a new item.  Each item runs with its own lane width:
+// 4 words (unit-stride rows, ragged or not) or 1.
 // ---------------------------------------------------------------------
 template <int OP, int U, int CP>
 __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ plans,
                                                      const uint32_t *__restrict__ ustart,
-                                                     uint32_t nitems, uint32_t total)
+                                                     uint32_t nitems, uint32_t total, uint32_t rr)
 {
     const uint32_t lb = logical_block();
     const uint32_t g = gridDim.x;
-    const uint32_t u0 = (uint32_t)(((uint64_t)lb * total) / g);
-    const uint32_t u1 = (uint32_t)(((uint64_t)(lb + 1) * total) / g);
-    if (u0 >= u1)
-        return;
-    uint32_t lo = 0, hi = nitems;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (ustart[mid] <= u0)
-            lo = mid;
-        else
-            hi = mid;
+    uint32_t u, uend, step;
+    if (rr) {
+        u = lb;
+        uend = total;
+        step = g;
+    } else {
+        u = (uint32_t)(((uint64_t)lb * total) / g);
+        uend = (uint32_t)(((uint64_t)(lb + 1) * total) / g);
+        step = 1;
     }
     // The current item's plan lives in LDS (one coalesced copy per item), so
     // the per-unit decode never waits on global memory.
     __shared__ CoPlan Ps;
-    uint32_t item = lo;
-    uint32_t first = ustart[item], next = ustart[item + 1];
-    bool loaded = false;
-    for (uint32_t u = u0; u < u1; ++u) {
-        if (u >= next || !loaded) {
-            while (u >= next) {
-                ++item;
-                first = next;
-                next = ustart[item + 1];
+    uint32_t item = 0, first = 0, next = 0;    // next == 0: nothing loaded yet
+    for (; u < uend; u += step) {
+        if (u >= next) {
+            // the item holding u: the last one whose first unit is <= u
+            // (empty items share their first unit with the next item)
+            uint32_t lo = item, hi = nitems;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (ustart[mid] <= u)
+                    lo = mid;
+                else
+                    hi = mid;
             }
+            item = lo;
+            first = ustart[item];
+            next = ustart[item + 1];
             __syncthreads();
             const uint32_t *src = (const uint32_t *)(plans + item);
             uint32_t *dst = (uint32_t *)&Ps;
@@ -515,7 +525,6 @@ __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ 
             if (Ps.RB > 1)
                 fill_table<OpInfo<OP>::PRED>(Ps, RowTable{lds_rows, Ps.RB});
             __syncthreads();
-            loaded = true;
         }
         const CoPlan &P = Ps;
         const RowTable T{lds_rows, P.RB};
@@ -662,7 +671,7 @@ static void go_batched(BatchLaunch &B, hipStream_t st)
     B.launched = clamp_resident(
         B.blocks, resident_per_cu(reinterpret_cast<const void *>(kern), lds, occ), B.cus);
     hipLaunchKernelGGL(kern, dim3(B.launched), dim3(NT), lds, st, B.plans, B.ustart, B.nitems,
-                       B.total);
+                       B.total, B.rr);
 }
 
 template <int OP>

@@ -18,6 +18,7 @@ struct BatchLaunch {
     int blocks;               // requested grid (clamped to what fits at once)
     int cus;
     int cache;                // cache policy
+    uint32_t rr;              // 0: contiguous unit ranges per workgroup, 1: round-robin
     int launched;             // out: the grid launched
 };
 hipError_t launch_batched(int co_op, BatchLaunch &B, hipStream_t st);

@@ -643,7 +643,7 @@ triot_status plan_coiter(const Request &r, const Sched &s, int cus, CoLaunch *ou
     int64_t pe_cap = pe_target;
     if (RB == 1) {
         for (int k = 0; k < n; ++k)
-            pe_cap = std::min<int64_t>(pe_cap, ((int64_t(1) << 31) / ((int64_t)esz * is[k])) - 1);
+            pe_cap = std::min<int64_t>(pe_cap, ((int64_t(1) << 31) / ((int64_t)esz * is[k])) - 2);
     }
     pe_cap = std::max<int64_t>(pe_cap, 1);
     int64_t parts = (BE + pe_cap - 1) / pe_cap;

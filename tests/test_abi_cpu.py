@@ -169,6 +169,11 @@ def test_plan_ragged_rows():
     assert p["vec"] == 1 and p["row_tail"] == 0
     p = api.describe(L.OP_MUL_ACC, [(5, 2), (5, 3), (5, 3)])
     assert p["vec"] == 1 and p["row_tail"] == 0
+    # one row of 4190211 elements: 1047553 vectors in 1024 units of 1024, so
+    # the last unit holds only the ragged vector (its offsets are taken from
+    # the vector before the unit, never from before the row)
+    p = api.describe(L.OP_COPY, [(4190211,), (4190211,)], params=L.CopyParams(4))
+    assert p["vec"] == 4 and p["row_tail"] == 3 and p["units"] == 1024 and p["box_rows"] == 1
 
 
 def test_plan_box_split_limits():

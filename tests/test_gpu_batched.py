@@ -110,16 +110,20 @@ def test_batched_empty_and_errors():
     b.close()
 
 
-@pytest.mark.parametrize("cache,bpc,unit", [(0, 4, 4096), (1, 4, 4096), (2, 2, 64), (0, 8, 1 << 16),
-                                            (1, 1, 1024)])
-def test_batched_schedules(cache, bpc, unit):
-    announce("batched schedule cache=%d bpc=%d unit=%d" % (cache, bpc, unit))
+@pytest.mark.parametrize("cache,bpc,unit,order", [(0, 4, 4096, 0), (1, 4, 4096, 0), (2, 2, 64, 0),
+                                                  (0, 8, 1 << 16, 0), (1, 1, 1024, 0),
+                                                  (1, 1, 4096, 1), (1, 8, 4096, 1), (2, 2, 64, 1),
+                                                  (0, 4, 1 << 16, 1)])
+def test_batched_schedules(cache, bpc, unit, order):
+    """Every schedule gives the oracle's bits; unit order 1 deals the work
+    units of all items round-robin over the workgroups."""
+    announce("batched schedule cache=%d bpc=%d unit=%d order=%d" % (cache, bpc, unit, order))
     shapes = inputs.cfg4_shapes()[:300]
     xs_np = inputs.cfg4_values(shapes)
     xs = [torch.from_numpy(x).cuda() for x in xs_np]
     dsts = [torch.full(inputs.padded_shape(sx, sy), 7.0, device="cuda") for sx, sy in shapes]
     b = api.Batch()
-    b.set_schedule(cache_policy=cache, blocks_per_cu=bpc, unit_elems=unit)
+    b.set_schedule(cache_policy=cache, blocks_per_cu=bpc, unit_elems=unit, unit_order=order)
     b.apply(L.OP_EMBED_FILL, [[d_, x] for d_, x in zip(dsts, xs)])
     torch.cuda.synchronize()
     _check_items(dsts, xs_np, shapes)
@@ -129,7 +133,8 @@ def test_batched_schedules(cache, bpc, unit):
     torch.cuda.synchronize()
     _check_items(dsts, xs_np, shapes)
     # a new schedule drops the captured graph: replay needs a new apply
-    b.set_schedule(cache_policy=(cache + 1) % 3, blocks_per_cu=bpc, unit_elems=unit)
+    b.set_schedule(cache_policy=(cache + 1) % 3, blocks_per_cu=bpc, unit_elems=unit,
+                   unit_order=1 - order)
     with pytest.raises(L.TriotError):
         b.launch()
     for d_ in dsts:
@@ -145,7 +150,7 @@ def test_batched_schedule_rejects_out_of_range():
     announce("batched schedule errors")
     b = api.Batch()
     for kw in ({"cache_policy": 3}, {"blocks_per_cu": 0}, {"blocks_per_cu": 33},
-               {"unit_elems": 63}, {"box_rows_max": 0}):
+               {"unit_elems": 63}, {"box_rows_max": 0}, {"unit_order": 2}):
         with pytest.raises(L.TriotError) as e:
             b.set_schedule(**kw)
         assert e.value.status == L.E_INVALID

@@ -193,3 +193,78 @@ def test_embed_fill_vectors_with_ragged_rows_and_bounds(case, vec):
     api.apply(L.OP_EMBED_FILL, [g, gx], shapes, dst_s, [0, shift], L.CopyParams(4),
               what="embed_fill")
     assert bits_equal(host(g), want), first_mismatch(host(g), want)
+
+
+# Short source rows (fewer elements than a vector) under vector lanes: the
+# source is read word by word.
+SHORT_FILL_CASES = [
+    ((9, 11), (7, 3), 0),
+    ((6, 9), (6, 1), 1),
+    ((5, 14), (5, 2), 0),
+    ((4, 3, 10), (4, 2, 3), 2),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SHORT_FILL_CASES)))
+def test_embed_fill_short_source_rows(case):
+    dst_s, src_s, shift = SHORT_FILL_CASES[case]
+    announce("fill short source rows", dst_s, src_s, shift)
+    rng = np.random.default_rng(950 + case)
+    parent = tuple(src_s[:-1]) + (src_s[-1] + shift,)
+    x = rng.standard_normal(parent).astype(np.float32)
+    want = np.full(dst_s, 7.0, dtype=np.float32)
+    oracle.embed_fill(dst_s, want.reshape(-1), dst_s, x.reshape(-1), parent, 0, shift)
+    g = torch.full(dst_s, 7.0, dtype=torch.float32, device="cuda")
+    gx = dev(x)
+    shapes = [dst_s, parent]
+    plan = api.describe(L.OP_EMBED_FILL, shapes, counter=dst_s, ptrs=[g.data_ptr(), gx.data_ptr()],
+                        bases=[0, shift], params=L.CopyParams(4))
+    assert plan["vec"] == 4, plan
+    api.apply(L.OP_EMBED_FILL, [g, gx], shapes, dst_s, [0, shift], L.CopyParams(4),
+              what="embed_fill")
+    assert bits_equal(host(g), want), first_mismatch(host(g), want)
+
+
+# One row of 4190211 elements: 1047553 four-word vectors, the last ragged
+# (3 words), in 1024 work units of 1024 vectors: the last unit holds only
+# the ragged vector.  Sources of the fills end inside the first vector of a
+# unit (element 4096 * 500 + 2) and inside the ragged vector.
+ROW = 4190211
+
+
+def _one_row_plan(op, tensors, shapes, params=None):
+    plan = api.describe(op, shapes, ptrs=[t.data_ptr() for t in tensors], params=params)
+    assert plan["vec"] == 4 and plan["row_tail"] == 3 and plan["units"] == 1024, plan
+    assert plan["box_rows"] == 1, plan
+
+
+def test_unit_starting_at_a_ragged_vector_or_a_straddle():
+    rng = np.random.default_rng(990)
+    announce("one-row copy, last unit = ragged vector", ROW)
+    src = rng.standard_normal(ROW).astype(np.float32)
+    dst = np.full(ROW, 3.0, dtype=np.float32)
+    g, gs = dev(dst), dev(src)
+    _one_row_plan(L.OP_COPY, [g, gs], [(ROW,), (ROW,)], L.CopyParams(4))
+    api.copy_(g, gs)
+    assert bits_equal(host(g), src), first_mismatch(host(g), src)
+
+    announce("one-row mul_acc", ROW)
+    y = rng.standard_normal(ROW).astype(np.float32)
+    z = rng.standard_normal(ROW).astype(np.float32)
+    want = src.copy()
+    oracle.mul_acc((ROW,), want, (ROW,), y, (ROW,), z, (ROW,))
+    gx, gy, gz = dev(src), dev(y), dev(z)
+    _one_row_plan(L.OP_MUL_ACC, [gx, gy, gz], [(ROW,)] * 3)
+    api.mul_acc_(gx, gy, gz)
+    assert bits_equal(host(gx), want), first_mismatch(host(gx), want)
+
+    for n_src in (4096 * 500 + 2, ROW - 1, ROW - 2):
+        announce("one-row fill", ROW, n_src)
+        x = rng.standard_normal(n_src).astype(np.float32)
+        want = np.full(ROW, 7.0, dtype=np.float32)
+        oracle.embed_fill((ROW,), want, (ROW,), x, (n_src,))
+        g = torch.full((ROW,), 7.0, dtype=torch.float32, device="cuda")
+        gx = dev(x)
+        _one_row_plan(L.OP_EMBED_FILL, [g, gx], [(ROW,), (n_src,)], L.CopyParams(4))
+        api.embed_fill_(g, gx)
+        assert bits_equal(host(g), want), first_mismatch(host(g), want)
