@@ -105,12 +105,27 @@ void *flush_buffer()
     return p;
 }
 
+// The default schedule of an element-wise problem.  Large streaming
+// problems (at least 2^25 counter points) take one workgroup per CU and
+// units dealt round-robin, so that the grid sweeps one window of memory
+// with few concurrent streams; smaller ones keep 4 workgroups per CU (more
+// waves in flight) and contiguous unit ranges.
+static Sched default_sched(const Request &r)
+{
+    Sched s;
+    if (r.npoints >= (int64_t(1) << 25)) {
+        s.blocks_per_cu = 1;
+        s.order = 1;
+    }
+    return s;
+}
+
 Sched sched_for(const Request &r)
 {
     std::lock_guard<std::mutex> g(g_mu);
     ensure_loaded();
     auto it = g_sched.find(sched_key(r));
-    return it == g_sched.end() ? Sched() : it->second;
+    return it == g_sched.end() ? default_sched(r) : it->second;
 }
 
 triot_status to_status(hipError_t e)
@@ -412,7 +427,7 @@ extern "C" triot_status triot_autotune(triot_op op, int n_tensors, int d, const 
         *ms = v[reps / 2];
         return TRIOT_OK;
     };
-    Sched best;
+    Sched best = default_sched(r);
     float best_ms = 0.f;
     st = time_it(best, &best_ms);
     // Coordinate descent over the knobs, each from the best so far.

@@ -176,6 +176,25 @@ def test_plan_ragged_rows():
     assert p["vec"] == 4 and p["row_tail"] == 3 and p["units"] == 1024 and p["box_rows"] == 1
 
 
+def test_default_schedules_by_problem_size():
+    """Without a pinned or tuned schedule: 4 workgroups per CU and
+    contiguous unit ranges, or 1 per CU and round-robin units from 2^25
+    counter points on (no device work)."""
+    def get(shapes):
+        ptrs = [(k + 1) << 40 for k in range(len(shapes))]
+        st, sch = L.triot_schedule_get(L.OP_MUL_ACC, len(shapes), len(shapes[0]), shapes, None,
+                                       ptrs, None, None)
+        assert st == L.OK
+        return (sch.vec_max, sch.cache_policy, sch.blocks_per_cu, sch.box_rows_max,
+                sch.unit_elems, sch.unit_order)
+    api.tune_reset()
+    assert get([(8, 40)] * 3) == (4, 1, 4, 1024, 8192, 0)
+    assert get([(1 << 12, (1 << 13) - 1)] * 3) == (4, 1, 4, 1024, 8192, 0)
+    assert get([(1 << 12, 1 << 13)] * 3) == (4, 1, 1, 1024, 8192, 1)
+    # the counter, not the operands, decides: a small window of large tensors
+    assert get([(1 << 12, 8), (1 << 13, 1 << 13), (1 << 13, 1 << 13)]) == (4, 1, 4, 1024, 8192, 0)
+
+
 def test_plan_box_split_limits():
     # very short rows: the box tabulates several low axes (bounded table)
     p = api.describe(L.OP_COPY, [(9, 5, 13, 21, 14, 6, 3, 25)] * 1 + [(10, 6, 14, 22, 15, 7, 4, 26)],
