@@ -309,8 +309,9 @@ triot_status triot_schedule_set(triot_op op, int n_tensors, int d, const int64_t
 /* The schedule triot_apply uses for this problem: the one pinned or tuned
  * for its plan signature, else the defaults (4-word lanes where the rows
  * allow, non-temporal loads and stores, units of 8192 lanes, 1024 box
- * rows; 4 workgroups per CU and contiguous unit ranges, or for at least
- * 2^25 counter points 1 workgroup per CU and round-robin units).  Same
+ * rows; 4 workgroups per CU and contiguous unit ranges, or for a COPY,
+ * MUL_ACC, MUL or XPYX_MZ of at least 2^25 counter points 1 workgroup per
+ * CU and round-robin units).  Same
  * arguments and errors as triot_schedule_set; no device work. */
 triot_status triot_schedule_get(triot_op op, int n_tensors, int d, const int64_t *shapes,
                                 const int64_t *counter_shape, void *const *tensors,

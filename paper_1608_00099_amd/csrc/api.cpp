@@ -105,15 +105,18 @@ void *flush_buffer()
     return p;
 }
 
-// The default schedule of an element-wise problem.  Large streaming
-// problems (at least 2^25 counter points) take one workgroup per CU and
+// The default schedule of an element-wise problem.  Large streaming copies
+// and products (at least 2^25 counter points) take one workgroup per CU and
 // units dealt round-robin, so that the grid sweeps one window of memory
-// with few concurrent streams; smaller ones keep 4 workgroups per CU (more
-// waves in flight) and contiguous unit ranges.
+// with few concurrent streams; smaller ones, and the other ops (EMBED_FILL
+// writes mostly zeros: 4 workgroups per CU keep more stores in flight),
+// keep 4 workgroups per CU and contiguous unit ranges.
 static Sched default_sched(const Request &r)
 {
     Sched s;
-    if (r.npoints >= (int64_t(1) << 25)) {
+    const bool streaming = r.op == TRIOT_OP_COPY || r.op == TRIOT_OP_MUL_ACC ||
+                           r.op == TRIOT_OP_MUL || r.op == TRIOT_OP_XPYX_MZ;
+    if (streaming && r.npoints >= (int64_t(1) << 25)) {
         s.blocks_per_cu = 1;
         s.order = 1;
     }

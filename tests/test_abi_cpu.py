@@ -178,12 +178,12 @@ def test_plan_ragged_rows():
 
 def test_default_schedules_by_problem_size():
     """Without a pinned or tuned schedule: 4 workgroups per CU and
-    contiguous unit ranges, or 1 per CU and round-robin units from 2^25
-    counter points on (no device work)."""
-    def get(shapes):
+    contiguous unit ranges, or, for copies and products of at least 2^25
+    counter points, 1 per CU and round-robin units (no device work)."""
+    def get(shapes, op=L.OP_MUL_ACC, params=None):
         ptrs = [(k + 1) << 40 for k in range(len(shapes))]
-        st, sch = L.triot_schedule_get(L.OP_MUL_ACC, len(shapes), len(shapes[0]), shapes, None,
-                                       ptrs, None, None)
+        st, sch = L.triot_schedule_get(op, len(shapes), len(shapes[0]), shapes, None,
+                                       ptrs, None, params)
         assert st == L.OK
         return (sch.vec_max, sch.cache_policy, sch.blocks_per_cu, sch.box_rows_max,
                 sch.unit_elems, sch.unit_order)
@@ -193,6 +193,10 @@ def test_default_schedules_by_problem_size():
     assert get([(1 << 12, 1 << 13)] * 3) == (4, 1, 1, 1024, 8192, 1)
     # the counter, not the operands, decides: a small window of large tensors
     assert get([(1 << 12, 8), (1 << 13, 1 << 13), (1 << 13, 1 << 13)]) == (4, 1, 4, 1024, 8192, 0)
+    big = [(1 << 12, 1 << 13)] * 2
+    assert get(big, L.OP_COPY, L.CopyParams(4)) == (4, 1, 1, 1024, 8192, 1)
+    # a large EMBED_FILL keeps 4 workgroups per CU and contiguous ranges
+    assert get(big, L.OP_EMBED_FILL, L.CopyParams(4)) == (4, 1, 4, 1024, 8192, 0)
 
 
 def test_plan_box_split_limits():
