@@ -49,10 +49,13 @@ def test_batched_fft_padding_full_4096_items():
     b.close()
 
 
-def test_batched_replan_and_other_ops():
-    announce("batched mixed ops")
+@pytest.mark.parametrize("order", [1, 0])
+def test_batched_replan_and_other_ops(order):
+    announce("batched mixed ops", order)
     rng = np.random.default_rng(9)
     b = api.Batch()
+    if order != 1:
+        b.set_schedule(unit_order=order)
     # MUL_ACC over intersections of ragged items of every d
     xs, ys, zs, want = [], [], [], []
     for d in range(1, 7):
