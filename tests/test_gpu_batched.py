@@ -197,3 +197,33 @@ def test_batched_lane_widths_agree():
         for it, w in zip(items, want):
             assert it[0].cpu().numpy().tobytes() == w.tobytes()
         b.close()
+
+
+@pytest.mark.parametrize("bpc,unit", [(1, 64), (2, 256)])
+def test_batched_uneven_items_round_robin(bpc, unit):
+    """One large item among many tiny ones, units dealt round-robin: each
+    workgroup's consecutive units fall in items far apart, found by binary
+    search over the items' first units."""
+    announce("batched uneven items", bpc, unit)
+    rng = np.random.default_rng(77 + bpc)
+    shapes = [((1024, 1000), (700, 900))]
+    for k in range(300):
+        d = 1 + k % 3
+        dst_s = tuple(int(v) for v in rng.integers(1, 12, size=d))
+        src_s = tuple(int(rng.integers(1, s + 1)) for s in dst_s)
+        shapes.append((dst_s, src_s))
+    shapes.insert(150, ((33, 47, 29), (20, 40, 29)))
+    xs_np = [rng.standard_normal(sx).astype(np.float32) for _, sx in shapes]
+    dsts = [torch.full(ds, 7.0, device="cuda") for ds, _ in shapes]
+    xs = [torch.from_numpy(x).cuda() for x in xs_np]
+    b = api.Batch()
+    b.set_schedule(blocks_per_cu=bpc, unit_elems=unit, unit_order=1)
+    b.apply(L.OP_EMBED_FILL, [[d_, x] for d_, x in zip(dsts, xs)])
+    torch.cuda.synchronize()
+    assert b.info()["units"] > b.info()["blocks"]
+    for i, (d_, x, (ds, sx)) in enumerate(zip(dsts, xs_np, shapes)):
+        want = np.full(ds, 7.0, dtype=np.float32)
+        oracle.embed_fill(ds, want.reshape(-1), ds, x.reshape(-1), sx)
+        got = d_.cpu().numpy()
+        assert got.tobytes() == want.tobytes(), ("item", i, ds, sx)
+    b.close()
