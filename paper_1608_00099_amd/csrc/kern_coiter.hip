@@ -168,8 +168,9 @@ template <> struct OpInfo<CO_MUL_ADJ> { static constexpr int N = 5; static const
 template <> struct OpInfo<CO_INDEX> { static constexpr int N = MAXT; static constexpr bool PRED = false; };
 template <> struct OpInfo<CO_XPYX_MZ> { static constexpr int N = 3; static constexpr bool PRED = false; };
 
-// Process one work unit (a part of one box).
-template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP, bool RAG>
+// Process one work unit (a part of one box).  BATCH: called from the batched
+// kernel (which keeps EMBED_FILL's lower-register body, see below).
+template <int OP, int V, int U, bool ROWS1, bool UNIT, int CP, bool RAG, bool BATCH = false>
 __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const RowTable &T)
 {
     typedef typename Vec<V>::U VU;
@@ -319,10 +320,69 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
             for (int u = 0; u < U; ++u)
                 if (valid[u])
                     gstore<VU, CP>(bp[0], off[0][u], v[u]);
-        } else if constexpr (OP == CO_FILL) {
+        } else if constexpr (OP == CO_FILL && !BATCH) {
             // Vectors: the source's inner bound is checked per word (ibel);
             // the destination vector, a ragged row's last included, is
-            // stored whole (shared words get the same value twice).
+            // stored whole (shared words get the same value twice).  The
+            // registers of a vector are written by loads only (a vector
+            // straddling the bound loads its words, the ones past the bound
+            // from the last word before it) and words outside the source
+            // are zeroed after the step's loads: no register is written by
+            // an ALU instruction while a load to it may be in flight in
+            // another lane, so the step waits for its loads once, before
+            // its stores (one counter covers loads and stores: a wait
+            // between them would also wait for the stores already issued).
+            VU v[U];
+            bool keep[U][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                asm volatile("" : "=v"(v[u]));   // defined without an instruction
+                const bool rd = valid[u] && (pm[u] & 2u);
+                if constexpr (V == 1) {
+                    keep[u][0] = rd;
+                    if (rd)
+                        v[u] = gload<VU, CP>(bp[1], off[1][u]);
+                } else {
+                    const uint32_t jel = jj[u] * V - (tl[u] ? P.tskip : 0u);
+                    // word addresses formed before any load of the step, in
+                    // registers no load of it writes
+                    uint32_t wa[V];
+                    const uint32_t last = P.ibel - 1u - jel;   // < V - 1 where used
+#pragma unroll
+                    for (int c = 0; c < V; ++c) {
+                        keep[u][c] = rd && jel + (uint32_t)c < P.ibel;
+                        wa[c] = off[1][u] + 4u * min((uint32_t)c, last);
+                        asm volatile("" : "+v"(wa[c]));
+                    }
+                    if (rd && jel + V <= P.ibel) {
+                        v[u] = gload<VU, CP>(bp[1], off[1][u]);
+                    } else if (rd && jel < P.ibel) {
+#pragma unroll
+                        for (int c = 0; c < V; ++c)
+                            v[u][c] = gload<uint32_t, CP>(bp[1], wa[c]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if constexpr (V == 1) {
+                    v[u] = keep[u][0] ? v[u] : (VU)0u;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < V; ++c)
+                        v[u][c] = keep[u][c] ? v[u][c] : 0u;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u])
+                    gstore<VU, CP>(bp[0], off[0][u], v[u]);
+        } else if constexpr (OP == CO_FILL) {
+            // The batched kernel's body: the same values with fewer
+            // registers (its instance holds every lane-width variant, and
+            // the body above would cost it two of eight workgroups per CU,
+            // more than the waits it saves).  A straddling vector loads its
+            // words in place, which waits for loads in flight.
             VU v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -534,25 +594,25 @@ __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ 
             // 4-word lanes: unit-stride rows, possibly ragged
             if (P.tskip) {
                 if (rows1)
-                    run_unit<OP, 4, U, true, true, CP, true>(P, lu, T);
+                    run_unit<OP, 4, U, true, true, CP, true, true>(P, lu, T);
                 else
-                    run_unit<OP, 4, U, false, true, CP, true>(P, lu, T);
+                    run_unit<OP, 4, U, false, true, CP, true, true>(P, lu, T);
             } else {
                 if (rows1)
-                    run_unit<OP, 4, U, true, true, CP, false>(P, lu, T);
+                    run_unit<OP, 4, U, true, true, CP, false, true>(P, lu, T);
                 else
-                    run_unit<OP, 4, U, false, true, CP, false>(P, lu, T);
+                    run_unit<OP, 4, U, false, true, CP, false, true>(P, lu, T);
             }
         } else if (rows1) {
             if (P.unit)
-                run_unit<OP, 1, U, true, true, CP, false>(P, lu, T);
+                run_unit<OP, 1, U, true, true, CP, false, true>(P, lu, T);
             else
-                run_unit<OP, 1, U, true, false, CP, false>(P, lu, T);
+                run_unit<OP, 1, U, true, false, CP, false, true>(P, lu, T);
         } else {
             if (P.unit)
-                run_unit<OP, 1, U, false, true, CP, false>(P, lu, T);
+                run_unit<OP, 1, U, false, true, CP, false, true>(P, lu, T);
             else
-                run_unit<OP, 1, U, false, false, CP, false>(P, lu, T);
+                run_unit<OP, 1, U, false, false, CP, false, true>(P, lu, T);
         }
     }
 }
