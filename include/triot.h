@@ -23,8 +23,9 @@
  *     (Section 4).  Errors are returned as triot_status, never aborted.
  *   - d = 0 is a scalar (one point, the empty tuple).  A counter with an
  *     extent 0 has no points: the call returns TRIOT_OK and does nothing.
- *     Extent-1 axes are dropped before planning (Section 4: trivial axes
- *     "can simply be ignored").
+ *     Extent-1 axes are dropped before planning (Section 4: an axis of
+ *     extent 1 adds nothing to any offset, so leaving it out changes no
+ *     result).
  *   - Window bounds: base_k decodes (in operand k's shape) to a start
  *     tuple sigma^k; every operand that is read or written on the whole
  *     counter needs sigma^k_i + counter_i <= s^k_i on every axis i.
@@ -240,7 +241,10 @@ void triot_batch_destroy(triot_batch *handle);
  * the table and captures the launch in a hipGraph; later calls with the
  * same shapes, pointers and op replay the graph on `stream`; a different
  * batch re-plans.  Supported ops: COPY, EMBED_FILL, MUL_ACC, MUL.
- * params as in triot_apply (shared by all items).  TRIOT_E_UNSUPPORTED
+ * params as in triot_apply (shared by all items).  Items run concurrently:
+ * TRIOT_E_ALIAS when the output range of one item overlaps any operand
+ * range (read or written) of another item, besides the per-item aliasing
+ * rule of triot_apply; nothing is enqueued then.  TRIOT_E_UNSUPPORTED
  * when the work units of all items reach 2^31. */
 triot_status triot_apply_batched(triot_op op, int n_items, const triot_item *items,
                                  const void *params, triot_batch *handle, hipStream_t stream);
@@ -328,6 +332,36 @@ triot_status triot_schedule_get(triot_op op, int n_tensors, int d, const int64_t
  * lanes, 1024 box rows, round-robin units.  TRIOT_E_INVALID for a knob out
  * of range. */
 triot_status triot_batch_set_schedule(triot_batch *handle, const triot_schedule *schedule);
+
+/* The schedule a batch handle plans with: the one set by
+ * triot_batch_set_schedule or chosen by triot_batch_autotune, else the
+ * default above (a schedule tuned earlier for the same batch layout on
+ * another handle is used by triot_apply_batched but not reported here).
+ * No device work.  TRIOT_E_INVALID for null arguments. */
+triot_status triot_batch_get_schedule(const triot_batch *handle, triot_schedule *schedule);
+
+/* Autotuner of the batched persistent launch (the schedules of its work
+ * table: the zero padding of thousands of ragged items ahead of FFT
+ * convolutions, Section 3, in one launch).  Validates the batch as
+ * triot_apply_batched does (same errors), then times the one persistent
+ * launch of this batch on `stream` under candidate schedules -- lane width
+ * (4 or 1 words), cache policy, workgroups per CU, work-unit size and unit
+ * order, by coordinate descent from the handle's current schedule, two
+ * passes -- each cold, after a write over a 512 MiB device buffer as in
+ * triot_autotune.  The fastest becomes the handle's schedule (as if set by
+ * triot_batch_set_schedule: the next triot_apply_batched plans and
+ * captures with it), is remembered in memory for every later batch with
+ * the same layout (op, element size, and every item's shapes, counter,
+ * bases and address alignment; not the addresses), and is appended to the
+ * JSON cache at cache_path (NULL = in memory only; TRIOT_TUNE_CACHE loads
+ * such entries too).  The operation RUNS several times on the given
+ * buffers: pass scratch copies for in-place ops (MUL_ACC).  Allocates
+ * device memory for the candidate tables and frees it before returning;
+ * synchronises `stream`.  A batch with no points returns TRIOT_OK and
+ * changes nothing. */
+triot_status triot_batch_autotune(triot_batch *handle, triot_op op, int n_items,
+                                  const triot_item *items, const void *params,
+                                  hipStream_t stream, const char *cache_path);
 
 /* ---- diagnostics -------------------------------------------------------- */
 

@@ -84,6 +84,7 @@ _lib = None
 
 EXPORTS = ["triot_apply", "triot_workspace_size", "triot_batch_create", "triot_batch_destroy",
            "triot_apply_batched", "triot_batch_launch", "triot_batch_info", "triot_batch_set_schedule",
+           "triot_batch_get_schedule", "triot_batch_autotune",
            "triot_autotune", "triot_tune_reset", "triot_schedule_set", "triot_schedule_get",
            "triot_status_string", "triot_divmod_magic", "triot_plan_describe"]
 
@@ -116,6 +117,10 @@ def lib():
     L.triot_batch_info.argtypes = [P, pI64, ctypes.POINTER(I), ctypes.POINTER(I)]
     L.triot_batch_set_schedule.restype = I
     L.triot_batch_set_schedule.argtypes = [P, ctypes.POINTER(Schedule)]
+    L.triot_batch_get_schedule.restype = I
+    L.triot_batch_get_schedule.argtypes = [P, ctypes.POINTER(Schedule)]
+    L.triot_batch_autotune.restype = I
+    L.triot_batch_autotune.argtypes = [P, I, I, ctypes.POINTER(Item), P, P, ctypes.c_char_p]
     L.triot_autotune.restype = I
     L.triot_autotune.argtypes = [I, I, I, pI64, pI64, pP, pI64, P, P, P, SZ, P, ctypes.c_char_p]
     L.triot_tune_reset.restype = None
@@ -245,10 +250,15 @@ def triot_batch_set_schedule(handle, schedule) -> int:
     return lib().triot_batch_set_schedule(handle, ctypes.byref(schedule))
 
 
-def triot_apply_batched(op, items, params, handle, stream) -> int:
-    """items: list of (d, n_tensors, shapes, counter_shape or None, ptrs, bases or None).
-    The marshalled arrays live until the call returns (the library copies
-    what it keeps)."""
+def triot_batch_get_schedule(handle):
+    sch = Schedule()
+    st = lib().triot_batch_get_schedule(handle, ctypes.byref(sch))
+    return st, sch
+
+
+def _items_array(items):
+    """Marshal [(d, n_tensors, shapes, counter_shape or None, ptrs, bases or
+    None)] into a triot_item array; returns it with the arrays it points to."""
     keep = []
     arr = (Item * max(len(items), 1))()
     for i, (d, n, shapes, counter, ptrs, bases) in enumerate(items):
@@ -263,6 +273,24 @@ def triot_apply_batched(op, items, params, handle, stream) -> int:
         arr[i].counter_shape = ctypes.cast(ct, ctypes.POINTER(ctypes.c_int64)) if ct is not None else None
         arr[i].tensors = ctypes.cast(pt, ctypes.POINTER(ctypes.c_void_p))
         arr[i].bases = ctypes.cast(bs, ctypes.POINTER(ctypes.c_int64)) if bs is not None else None
+    return arr, keep
+
+
+def triot_batch_autotune(handle, op, items, params, stream, cache_path=None) -> int:
+    """items as for triot_apply_batched."""
+    arr, keep = _items_array(items)
+    st = lib().triot_batch_autotune(handle, int(op), len(items), arr, _params_ptr(params),
+                                    ctypes.c_void_p(int(stream) if stream else 0),
+                                    cache_path.encode() if cache_path else None)
+    del keep
+    return st
+
+
+def triot_apply_batched(op, items, params, handle, stream) -> int:
+    """items: list of (d, n_tensors, shapes, counter_shape or None, ptrs, bases or None).
+    The marshalled arrays live until the call returns (the library copies
+    what it keeps)."""
+    arr, keep = _items_array(items)
     st = lib().triot_apply_batched(int(op), len(items), arr, _params_ptr(params), handle,
                                    ctypes.c_void_p(int(stream) if stream else 0))
     del keep

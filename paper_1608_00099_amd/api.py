@@ -331,13 +331,17 @@ class Batch:
         if not items:
             return
         dev = items[0][0].device
-        marshalled = []
+        params = L.CopyParams(elem_bytes) if op in (L.OP_COPY, L.OP_EMBED_FILL) else None
+        st = L.triot_apply_batched(op, self._marshal(items), params, self._h, _stream(dev))
+        _check(st, "apply_batched")
+
+    @staticmethod
+    def _marshal(items):
+        out = []
         for ops in items:
             shapes = [tuple(t.shape) for t in ops]
-            marshalled.append((len(shapes[0]), len(ops), shapes, None, [_ptr(t) for t in ops], None))
-        params = L.CopyParams(elem_bytes) if op in (L.OP_COPY, L.OP_EMBED_FILL) else None
-        st = L.triot_apply_batched(op, marshalled, params, self._h, _stream(dev))
-        _check(st, "apply_batched")
+            out.append((len(shapes[0]), len(ops), shapes, None, [_ptr(t) for t in ops], None))
+        return out
 
     def set_schedule(self, cache_policy=1, blocks_per_cu=8, box_rows_max=1024, unit_elems=4096,
                      vec_max=4, unit_order=1):
@@ -346,6 +350,24 @@ class Batch:
         sch = L.Schedule(vec_max, cache_policy, blocks_per_cu, box_rows_max, unit_elems,
                          unit_order)
         _check(L.triot_batch_set_schedule(self._h, sch), "batch_set_schedule")
+
+    def autotune(self, op, items, elem_bytes=4, cache_path=None):
+        """Time candidate schedules of this batch's persistent launch (cold)
+        and keep the fastest on this handle (the op runs several times on
+        the given buffers)."""
+        if not items:
+            return
+        dev = items[0][0].device
+        params = L.CopyParams(elem_bytes) if op in (L.OP_COPY, L.OP_EMBED_FILL) else None
+        st = L.triot_batch_autotune(self._h, op, self._marshal(items), params, _stream(dev),
+                                    cache_path)
+        _check(st, "batch_autotune")
+
+    def schedule(self):
+        """The schedule this handle plans with (dict of triot_schedule)."""
+        st, sch = L.triot_batch_get_schedule(self._h)
+        _check(st, "batch_get_schedule")
+        return {f: getattr(sch, f) for f, _ in L.Schedule._fields_}
 
     def launch(self, device=None):
         """Replay the last planned batch on the current stream (no

@@ -568,6 +568,7 @@ static Sched batch_default_sched()
 struct triot_batch {
     std::vector<int64_t> sig;     // what the captured graph was built for
     Sched sched = batch_default_sched();
+    bool pinned = false;          // schedule set by triot_batch_set_schedule / autotune
     CoPlan *d_plans = nullptr;
     uint32_t *d_ustart = nullptr;
     hipGraph_t graph = nullptr;
@@ -596,6 +597,198 @@ static void batch_release(triot_batch *b)
     b->sig.clear();
 }
 
+// Whether an output of one item overlaps an operand (read or written) of
+// another item.  Outputs must be pairwise disjoint across items: sorted by
+// start, each must begin at or after the end of every earlier one of
+// another item.  Then every read range is looked up among the sorted,
+// disjoint outputs (their ends are sorted too): the first output ending
+// after the range's start is the only candidate that can begin before the
+// range's end.  O(R log R) for R ranges.
+struct Span {
+    uint64_t lo, hi;
+    int item;
+};
+
+static bool batch_items_overlap(const std::vector<Request> &reqs)
+{
+    std::vector<Span> outs, ins;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        const Request &r = reqs[i];
+        for (int k = 0; k < r.n; ++k) {
+            if (r.span_lo[k] == r.span_hi[k])
+                continue;
+            Span sp{r.span_lo[k], r.span_hi[k], (int)i};
+            (r.written[k] ? outs : ins).push_back(sp);
+        }
+    }
+    auto by_lo = [](const Span &a, const Span &b) { return a.lo < b.lo; };
+    std::sort(outs.begin(), outs.end(), by_lo);
+    // Outputs of one item never overlap each other (validate), so the
+    // running maximum end of the outputs before j tells whether any of
+    // them (of another item, or of the same item, which is then adjacent
+    // and disjoint) reaches past outs[j].lo.
+    uint64_t maxhi = 0;
+    int maxitem = -1;
+    for (const Span &o : outs) {
+        if (maxitem >= 0 && o.lo < maxhi && o.item != maxitem)
+            return true;
+        if (o.hi > maxhi) {
+            maxhi = o.hi;
+            maxitem = o.item;
+        }
+    }
+    for (const Span &in : ins) {
+        auto it = std::upper_bound(outs.begin(), outs.end(), in.lo,
+                                   [](uint64_t v, const Span &o) { return v < o.hi; });
+        for (; it != outs.end() && it->lo < in.hi; ++it)
+            if (it->item != in.item)
+                return true;
+    }
+    return false;
+}
+
+static bool batch_op_ok(triot_op op)
+{
+    return op == TRIOT_OP_COPY || op == TRIOT_OP_EMBED_FILL || op == TRIOT_OP_MUL_ACC ||
+           op == TRIOT_OP_MUL;
+}
+
+// Validate every item, then the items against each other: they run
+// concurrently inside one launch, so an output that overlaps any operand
+// of another item would race.  No device call.
+static triot_status batch_validate(triot_op op, int n_items, const triot_item *items,
+                                   const void *params, std::vector<Request> *reqs)
+{
+    if (n_items < 0 || (n_items > 0 && !items))
+        return TRIOT_E_INVALID;
+    if (!batch_op_ok(op))
+        return TRIOT_E_UNSUPPORTED;
+    reqs->assign((size_t)n_items, Request());
+    for (int i = 0; i < n_items; ++i) {
+        const triot_item &it = items[i];
+        triot_status st = validate(op, it.n_tensors, it.d, it.shapes, it.counter_shape, it.tensors,
+                                   it.bases, params, &(*reqs)[(size_t)i]);
+        if (st != TRIOT_OK)
+            return st;
+    }
+    return batch_items_overlap(*reqs) ? TRIOT_E_ALIAS : TRIOT_OK;
+}
+
+static int batch_elem_bytes(triot_op op, const void *params)
+{
+    return params && (op == TRIOT_OP_COPY || op == TRIOT_OP_EMBED_FILL)
+               ? ((const triot_copy_params *)params)->elem_bytes
+               : 4;
+}
+
+// Key of a batch's tuned schedule: the op and every item's plan signature
+// (shapes, counter, bases and alignments, not the addresses), hashed
+// (FNV-1a, 64 bits), so that the same layout in other buffers reuses it.
+static std::string batch_key(triot_op op, int elem_bytes, const std::vector<Request> &reqs)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const std::string &s) {
+        for (unsigned char c : s) {
+            h ^= c;
+            h *= 1099511628211ull;
+        }
+        h ^= 0xFF;
+        h *= 1099511628211ull;
+    };
+    for (const Request &r : reqs)
+        mix(sched_key(r));
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "batch:op%d:e%d:n%zu:h%016llx", (int)op, elem_bytes,
+                  reqs.size(), (unsigned long long)h);
+    return buf;
+}
+
+// Plans of the items with points, their first work units and the rows of
+// the largest multi-row box.
+struct BatchPlan {
+    std::vector<CoPlan> plans;
+    std::vector<uint32_t> ustart;
+    uint64_t total = 0;
+    uint32_t rows_max = 0;
+};
+
+static triot_status batch_plan(const std::vector<Request> &reqs, const Sched &s, int cus,
+                               BatchPlan *bp)
+{
+    bp->plans.clear();
+    bp->ustart.assign(1, 0);
+    bp->total = 0;
+    bp->rows_max = 0;
+    bp->plans.reserve(reqs.size());
+    for (const Request &r : reqs) {
+        if (r.npoints == 0)
+            continue;
+        CoLaunch L;
+        triot_status st = plan_coiter(r, s, cus, &L);
+        if (st != TRIOT_OK)
+            return st;
+        if (L.plan.vec != 1 && L.plan.vec != 4)
+            return TRIOT_E_UNSUPPORTED;   // the batched kernel runs 4- or 1-word lanes
+        if (L.plan.RB > 1)
+            bp->rows_max = std::max(bp->rows_max, L.plan.RB);
+        bp->plans.push_back(L.plan);
+        bp->total += L.plan.nunits;
+        if (bp->total >= (uint64_t(1) << 31))
+            return TRIOT_E_UNSUPPORTED;
+        bp->ustart.push_back((uint32_t)bp->total);
+    }
+    return TRIOT_OK;
+}
+
+static int batch_grid(const BatchPlan &bp, const Sched &s, int cus)
+{
+    int blocks = (int)std::min<uint64_t>(bp.total, (uint64_t)cus * std::max(1, s.blocks_per_cu));
+    if (blocks > 8)
+        blocks = (blocks + 7) / 8 * 8;
+    return blocks;
+}
+
+static BatchLaunch batch_launch_args(triot_op op, const BatchPlan &bp, const Sched &s, int cus,
+                                     const CoPlan *d_plans, const uint32_t *d_ustart)
+{
+    (void)op;
+    BatchLaunch B;
+    B.plans = d_plans;
+    B.ustart = d_ustart;
+    B.nitems = (uint32_t)bp.plans.size();
+    B.total = (uint32_t)bp.total;
+    B.rows_max = bp.rows_max;
+    B.blocks = batch_grid(bp, s, cus);
+    B.cus = cus;
+    B.cache = s.cache;
+    B.rr = s.order ? 1u : 0u;
+    B.launched = B.blocks;
+    return B;
+}
+
+// The schedule a batch runs with: the handle's own if one was set or
+// tuned on it, else one tuned earlier for the same batch layout, else the
+// default.
+static Sched batch_sched_for(const triot_batch *h, const std::string &key)
+{
+    if (h->pinned)
+        return h->sched;
+    std::lock_guard<std::mutex> g(g_mu);
+    ensure_loaded();
+    auto it = g_sched.find(key);
+    if (it == g_sched.end())
+        return h->sched;
+    // the knobs of the tuned entry on the batched kernel's fixed settings
+    Sched s = batch_default_sched();
+    s.vec_max = it->second.vec_max >= 4 ? 4 : 1;
+    s.cache = it->second.cache;
+    s.blocks_per_cu = it->second.blocks_per_cu;
+    s.rb_max = it->second.rb_max;
+    s.pe_target = it->second.pe_target;
+    s.order = it->second.order;
+    return s;
+}
+
 extern "C" triot_status triot_batch_create(triot_batch **handle)
 {
     if (!handle)
@@ -614,10 +807,8 @@ extern "C" void triot_batch_destroy(triot_batch *handle)
     delete handle;
 }
 
-extern "C" triot_status triot_batch_set_schedule(triot_batch *handle, const triot_schedule *schedule)
+static bool batch_sched_from(const triot_schedule *schedule, Sched *out)
 {
-    if (!handle || !schedule)
-        return TRIOT_E_INVALID;
     Sched s = batch_default_sched();
     s.vec_max = schedule->vec_max >= 4 ? 4 : 1;
     s.cache = schedule->cache_policy;
@@ -626,12 +817,44 @@ extern "C" triot_status triot_batch_set_schedule(triot_batch *handle, const trio
     s.pe_target = schedule->unit_elems;
     s.order = schedule->unit_order;
     if (!sched_valid(s))
-        return TRIOT_E_INVALID;
+        return false;
+    *out = s;
+    return true;
+}
+
+static void batch_set(triot_batch *handle, const Sched &s)
+{
     handle->sched = s;
+    handle->pinned = true;
     batch_release(handle);        // the next apply plans and captures afresh
     handle->device = -1;
     handle->units = 0;
     handle->blocks = 0;
+}
+
+extern "C" triot_status triot_batch_set_schedule(triot_batch *handle, const triot_schedule *schedule)
+{
+    if (!handle || !schedule)
+        return TRIOT_E_INVALID;
+    Sched s;
+    if (!batch_sched_from(schedule, &s))
+        return TRIOT_E_INVALID;
+    batch_set(handle, s);
+    return TRIOT_OK;
+}
+
+extern "C" triot_status triot_batch_get_schedule(const triot_batch *handle,
+                                                 triot_schedule *schedule)
+{
+    if (!handle || !schedule)
+        return TRIOT_E_INVALID;
+    const Sched &s = handle->sched;
+    schedule->vec_max = s.vec_max;
+    schedule->cache_policy = s.cache;
+    schedule->blocks_per_cu = s.blocks_per_cu;
+    schedule->box_rows_max = s.rb_max;
+    schedule->unit_elems = s.pe_target;
+    schedule->unit_order = s.order;
     return TRIOT_OK;
 }
 
@@ -668,31 +891,25 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
                                             const void *params, triot_batch *handle,
                                             hipStream_t stream)
 {
-    if (!handle || n_items < 0 || (n_items > 0 && !items))
+    if (!handle)
         return TRIOT_E_INVALID;
-    if (op != TRIOT_OP_COPY && op != TRIOT_OP_EMBED_FILL && op != TRIOT_OP_MUL_ACC &&
-        op != TRIOT_OP_MUL)
-        return TRIOT_E_UNSUPPORTED;
+    std::vector<Request> reqs;
+    triot_status vst = batch_validate(op, n_items, items, params, &reqs);
+    if (vst != TRIOT_OK)
+        return vst;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return TRIOT_E_DEVICE;
 
-    // Validate every item and build the signature of the batch.
-    std::vector<Request> reqs((size_t)n_items);
+    // The signature of the batch: what a captured graph replays.
+    const int eb = batch_elem_bytes(op, params);
     std::vector<int64_t> sig;
     sig.reserve((size_t)n_items * 16 + 4);
     sig.push_back((int64_t)op);
     sig.push_back(n_items);
     sig.push_back(dev);
-    sig.push_back(params && (op == TRIOT_OP_COPY || op == TRIOT_OP_EMBED_FILL)
-                      ? ((const triot_copy_params *)params)->elem_bytes
-                      : 4);
+    sig.push_back(eb);
     for (int i = 0; i < n_items; ++i) {
-        const triot_item &it = items[i];
-        triot_status st = validate(op, it.n_tensors, it.d, it.shapes, it.counter_shape, it.tensors,
-                                   it.bases, params, &reqs[(size_t)i]);
-        if (st != TRIOT_OK)
-            return st;
         const Request &r = reqs[(size_t)i];
         sig.push_back(r.d);
         sig.push_back(r.n);
@@ -714,51 +931,28 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
     // Plan every item with the batch's schedule (4- or 1-word lanes).
     batch_release(handle);
     handle->replayed = 0;
-    const Sched s = handle->sched;
+    const Sched s = batch_sched_for(handle, batch_key(op, eb, reqs));
     const int cus = device_cus();
-    std::vector<CoPlan> plans;
-    std::vector<uint32_t> ustart;
-    plans.reserve((size_t)n_items);
-    ustart.push_back(0);
-    uint64_t total = 0;
-    uint32_t rows_max = 0;
-    for (int i = 0; i < n_items; ++i) {
-        const Request &r = reqs[(size_t)i];
-        if (r.npoints == 0)
-            continue;
-        CoLaunch L;
-        triot_status st = plan_coiter(r, s, cus, &L);
-        if (st != TRIOT_OK)
-            return st;
-        if (L.plan.vec != 1 && L.plan.vec != 4)
-            return TRIOT_E_UNSUPPORTED;   // the batched kernel runs 4- or 1-word lanes
-        if (L.plan.RB > 1)
-            rows_max = std::max(rows_max, L.plan.RB);
-        plans.push_back(L.plan);
-        total += L.plan.nunits;
-        if (total >= (uint64_t(1) << 31))
-            return TRIOT_E_UNSUPPORTED;
-        ustart.push_back((uint32_t)total);
-    }
-    handle->units = (int64_t)total;
+    BatchPlan bp;
+    triot_status pst = batch_plan(reqs, s, cus, &bp);
+    if (pst != TRIOT_OK)
+        return pst;
+    handle->units = (int64_t)bp.total;
     handle->device = dev;
-    if (total == 0) {
+    if (bp.total == 0) {
         handle->blocks = 0;
         return TRIOT_OK;
     }
-    int blocks = (int)std::min<uint64_t>(total, (uint64_t)cus * std::max(1, s.blocks_per_cu));
-    if (blocks > 8)
-        blocks = (blocks + 7) / 8 * 8;
-    handle->blocks = blocks;
+    handle->blocks = batch_grid(bp, s, cus);
 
-    if (hipMalloc((void **)&handle->d_plans, plans.size() * sizeof(CoPlan)) != hipSuccess ||
-        hipMalloc((void **)&handle->d_ustart, ustart.size() * sizeof(uint32_t)) != hipSuccess) {
+    if (hipMalloc((void **)&handle->d_plans, bp.plans.size() * sizeof(CoPlan)) != hipSuccess ||
+        hipMalloc((void **)&handle->d_ustart, bp.ustart.size() * sizeof(uint32_t)) != hipSuccess) {
         batch_release(handle);
         return TRIOT_E_DEVICE;
     }
-    if (hipMemcpy(handle->d_plans, plans.data(), plans.size() * sizeof(CoPlan),
+    if (hipMemcpy(handle->d_plans, bp.plans.data(), bp.plans.size() * sizeof(CoPlan),
                   hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(handle->d_ustart, ustart.data(), ustart.size() * sizeof(uint32_t),
+        hipMemcpy(handle->d_ustart, bp.ustart.data(), bp.ustart.size() * sizeof(uint32_t),
                   hipMemcpyHostToDevice) != hipSuccess) {
         batch_release(handle);
         return TRIOT_E_DEVICE;
@@ -772,22 +966,11 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
     // Capture the single persistent launch on the library's own stream
     // (capture is not allowed on the null stream), then replay it on the
     // caller's.
-    const uint32_t nitems = (uint32_t)plans.size();
     if (hipStreamBeginCapture(handle->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         batch_release(handle);
         return TRIOT_E_DEVICE;
     }
-    BatchLaunch B;
-    B.plans = handle->d_plans;
-    B.ustart = handle->d_ustart;
-    B.nitems = nitems;
-    B.total = (uint32_t)total;
-    B.rows_max = rows_max;
-    B.blocks = blocks;
-    B.cus = cus;
-    B.cache = s.cache;
-    B.rr = s.order ? 1u : 0u;
-    B.launched = blocks;
+    BatchLaunch B = batch_launch_args(op, bp, s, cus, handle->d_plans, handle->d_ustart);
     hipError_t le = launch_batched(co_op_of(op), B, handle->cap);
     handle->blocks = B.launched;
     hipGraph_t graph = nullptr;
@@ -806,4 +989,145 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
     }
     handle->sig = std::move(sig);
     return to_status(hipGraphLaunch(handle->exec, stream));
+}
+
+// ---- batch autotuner ----------------------------------------------------
+
+extern "C" triot_status triot_batch_autotune(triot_batch *handle, triot_op op, int n_items,
+                                             const triot_item *items, const void *params,
+                                             hipStream_t stream, const char *cache_path)
+{
+    if (!handle)
+        return TRIOT_E_INVALID;
+    std::vector<Request> reqs;
+    triot_status st = batch_validate(op, n_items, items, params, &reqs);
+    if (st != TRIOT_OK)
+        return st;
+    const int cus = device_cus();
+    const std::string key = batch_key(op, batch_elem_bytes(op, params), reqs);
+    // Device tables sized once: the plan count and unit starts do not
+    // depend on the schedule (items with points, one plan each).
+    BatchPlan bp;
+    st = batch_plan(reqs, batch_default_sched(), cus, &bp);
+    if (st != TRIOT_OK)
+        return st;
+    if (bp.total == 0)
+        return TRIOT_OK;   // nothing to time
+    CoPlan *d_plans = nullptr;
+    uint32_t *d_ustart = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    auto cleanup = [&]() {
+        if (d_plans)
+            (void)hipFree(d_plans);
+        if (d_ustart)
+            (void)hipFree(d_ustart);
+        if (ev0)
+            (void)hipEventDestroy(ev0);
+        if (ev1)
+            (void)hipEventDestroy(ev1);
+    };
+    if (hipMalloc((void **)&d_plans, bp.plans.size() * sizeof(CoPlan)) != hipSuccess ||
+        hipMalloc((void **)&d_ustart, bp.ustart.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
+        cleanup();
+        return TRIOT_E_DEVICE;
+    }
+    // Cold timing, as triot_autotune: a write over a buffer larger than the
+    // memory-side cache precedes every timed launch.
+    void *flush = flush_buffer();
+    int flush_val = 0;
+    auto time_it = [&](const Sched &s, float *ms) -> triot_status {
+        BatchPlan p;
+        triot_status t = batch_plan(reqs, s, cus, &p);
+        if (t != TRIOT_OK)
+            return t;
+        if (p.plans.size() != bp.plans.size())
+            return TRIOT_E_DEVICE;     // cannot happen: one plan per item with points
+        if (hipMemcpyAsync(d_plans, p.plans.data(), p.plans.size() * sizeof(CoPlan),
+                           hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(d_ustart, p.ustart.data(), p.ustart.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice, stream) != hipSuccess)
+            return TRIOT_E_DEVICE;
+        BatchLaunch B = batch_launch_args(op, p, s, cus, d_plans, d_ustart);
+        if (launch_batched(co_op_of(op), B, stream) != hipSuccess)   // warm-up
+            return TRIOT_E_DEVICE;
+        const int reps = 5;
+        float v[reps];
+        for (int i = 0; i < reps; ++i) {
+            if ((flush && hipMemsetAsync(flush, ++flush_val & 0xFF, kFlushBytes, stream) !=
+                              hipSuccess) ||
+                hipEventRecord(ev0, stream) != hipSuccess)
+                return TRIOT_E_DEVICE;
+            B.launched = B.blocks;
+            if (launch_batched(co_op_of(op), B, stream) != hipSuccess)
+                return TRIOT_E_DEVICE;
+            if (hipEventRecord(ev1, stream) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess)
+                return TRIOT_E_DEVICE;
+            if (hipEventElapsedTime(&v[i], ev0, ev1) != hipSuccess)
+                return TRIOT_E_DEVICE;
+        }
+        std::sort(v, v + reps);
+        *ms = v[reps / 2];
+        // the host plan vectors of this candidate stay alive until the
+        // copies above have run
+        return hipStreamSynchronize(stream) == hipSuccess ? TRIOT_OK : TRIOT_E_DEVICE;
+    };
+    Sched best = handle->pinned ? handle->sched : batch_sched_for(handle, key);
+    float best_ms = 0.f;
+    st = time_it(best, &best_ms);
+    // Coordinate descent over the knobs of the batched kernel, each from the
+    // best so far, two passes.
+    const int vecs[] = {4, 1};
+    const int caches[] = {1, 0, 2};
+    const int bpcs[] = {2, 4, 8, 16};
+    const int orders[] = {1, 0};
+    const int pes[] = {1024, 2048, 4096, 8192, 16384};
+    for (int pass = 0; pass < 2 && st == TRIOT_OK; ++pass) {
+        auto sweep = [&](int Sched::*field, const int *vals, int nvals) {
+            for (int i = 0; i < nvals && st == TRIOT_OK; ++i) {
+                Sched s = best;
+                if (s.*field == vals[i])
+                    continue;
+                s.*field = vals[i];
+                float ms;
+                triot_status t = time_it(s, &ms);
+                if (t == TRIOT_E_UNSUPPORTED)
+                    continue;
+                if (t != TRIOT_OK) {
+                    st = t;
+                    return;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = s;
+                }
+            }
+        };
+        sweep(&Sched::vec_max, vecs, 2);
+        sweep(&Sched::cache, caches, 3);
+        sweep(&Sched::blocks_per_cu, bpcs, 4);
+        sweep(&Sched::order, orders, 2);
+        sweep(&Sched::pe_target, pes, 5);
+    }
+    cleanup();
+    if (st != TRIOT_OK)
+        return st;
+    batch_set(handle, best);
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        ensure_loaded();
+        g_sched[key] = best;
+    }
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "a");
+        if (f) {
+            std::fprintf(f,
+                         "{\"key\": \"%s\", \"vec\": %d, \"cache\": %d, \"bpc\": %d, "
+                         "\"order\": %d, \"rb\": %d, \"pe\": %d}\n",
+                         key.c_str(), best.vec_max, best.cache, best.blocks_per_cu, best.order,
+                         best.rb_max, best.pe_target);
+            std::fclose(f);
+        }
+    }
+    return TRIOT_OK;
 }

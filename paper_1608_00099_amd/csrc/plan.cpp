@@ -1,5 +1,5 @@
-// Host planner: one validation pass over shapes per call (Section 4 of the
-// paper: "a single check over shapes rather than over indices"), then the
+// Host planner: one validation pass over shapes per call (Section 4: the
+// bounds are checked once for the whole shapes, never per index), then the
 // launch plan -- dropped and merged axes, vector width, the box split and
 // the magic-division tables of the kernels.
 #include "plan.h"
@@ -334,6 +334,9 @@ triot_status validate(triot_op op, int n, int d, const int64_t *shapes, const in
             uint64_t p = (uint64_t)(uintptr_t)tensors[k];
             lo[k] = p + (uint64_t)r->base[k] * eb;
             hi[k] = empty ? lo[k] : lo[k] + (uint64_t)(span + 1) * eb;
+            r->span_lo[k] = lo[k];
+            r->span_hi[k] = hi[k];
+            r->written[k] = is_output(op, k);
         }
         for (int o = 0; o < n; ++o) {
             if (!is_output(op, o))

@@ -36,6 +36,11 @@ struct Request {
     int elem_bytes;                  // element size of COPY / EMBED_FILL (4 or 8), else 4
     int64_t npoints;                 // counter points
     const void *params;
+    // Byte range [span_lo, span_hi) each operand touches over the counter
+    // (empty when equal), and which operands are written; set by validate
+    // for the element-wise ops that check aliasing.
+    uint64_t span_lo[MAXT], span_hi[MAXT];
+    bool written[MAXT];
 };
 
 struct CoLaunch {

@@ -124,6 +124,22 @@ def uniform_torch(shape, seed: int, device):
 
 
 # ---------------------------------------------------------------------------
+# Benchmark 1 of the paper (Section 3): crop of a (2^10, 2^9, 2^8) tensor to
+# its leading (2^9, 2^9, 2^5) block
+# ---------------------------------------------------------------------------
+
+PAPER_B1_BIG = (1 << 10, 1 << 9, 1 << 8)
+PAPER_B1_SMALL = (1 << 9, 1 << 9, 1 << 5)
+
+
+def paper_b1_values(dtype=np.float64) -> np.ndarray:
+    """U[0,1) source of the crop in float32 or float64 (the paper's runs use
+    float64)."""
+    dt = np.dtype(dtype)
+    return rng(6, 0, dt.itemsize).random(PAPER_B1_BIG, dtype=dt)
+
+
+# ---------------------------------------------------------------------------
 # cfg3
 # ---------------------------------------------------------------------------
 

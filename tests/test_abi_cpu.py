@@ -222,3 +222,54 @@ def test_workspace_size():
     assert L.triot_workspace_size(L.OP_COPY, 2, 1, [(4,), (4,)]) == 0
     n = L.triot_workspace_size(L.OP_MOMENTS, 1, 6, [(16,) * 6])
     assert n > 256
+
+
+def _batched_status(op, items):
+    st, h = L.triot_batch_create()
+    assert st == L.OK
+    try:
+        return L.triot_apply_batched(op, items, None, h, 0)
+    finally:
+        L.triot_batch_destroy(h)
+
+
+def test_batched_rejects_overlap_across_items():
+    # Validation and the cross-item check run before any device call, so
+    # with fake addresses a rejected batch returns E_ALIAS here (a batch
+    # that passes would need a device and fails later with E_DEVICE).
+    sh = [(4, 4), (4, 4)]
+    n16 = 16 * 4   # bytes of one (4, 4) float32 tensor
+    # item 1 writes into item 0's source
+    items = [(2, 2, sh, None, [P0, P1], None), (2, 2, sh, None, [P1, P2], None)]
+    assert _batched_status(L.OP_COPY, items) == L.E_ALIAS
+    # two outputs overlap by one element
+    items = [(2, 2, sh, None, [P0, P1], None), (2, 2, sh, None, [P0 + n16 - 4, P2], None)]
+    assert _batched_status(L.OP_COPY, items) == L.E_ALIAS
+    # an output inside another item's window read (bases make the window)
+    items = [(2, 2, [(4, 4), (8, 8)], (4, 4), [P0, P1], [0, 4 * 8 + 4]),
+             (2, 2, [(2, 2), (2, 2)], None, [P1 + (5 * 8 + 5) * 4, P2], None)]
+    assert _batched_status(L.OP_EMBED_FILL, items) == L.E_ALIAS
+    # x += y*z with another item's x as its y
+    s3 = [(4, 4)] * 3
+    items = [(2, 3, s3, None, [P0, P1, P2], None), (2, 3, s3, None, [P3, P0, P4], None)]
+    assert _batched_status(L.OP_MUL_ACC, items) == L.E_ALIAS
+    # the same view in and out within one item stays legal, and so do
+    # inputs shared by several items and adjacent outputs: these pass the
+    # checks and stop only at the device query
+    ok = {L.E_DEVICE, L.OK}
+    items = [(2, 3, s3, None, [P0, P0, P2], None), (2, 3, s3, None, [P3, P2, P2], None)]
+    assert _batched_status(L.OP_MUL_ACC, items) in ok
+    items = [(2, 2, sh, None, [P0, P2], None), (2, 2, sh, None, [P0 + n16, P2], None)]
+    assert _batched_status(L.OP_COPY, items) in ok
+
+
+def test_batched_overlap_check_many_items():
+    # 512 items writing adjacent blocks and all reading one shared source:
+    # accepted by the checks; moving one output back by one element makes
+    # it overlap its neighbour.
+    n = 512
+    sh = [(8,), (8,)]
+    items = [(1, 2, sh, None, [P0 + 32 * i, P1], None) for i in range(n)]
+    assert _batched_status(L.OP_COPY, items) in {L.E_DEVICE, L.OK}
+    items[300] = (1, 2, sh, None, [P0 + 32 * 300 - 4, P1], None)
+    assert _batched_status(L.OP_COPY, items) == L.E_ALIAS

@@ -227,3 +227,98 @@ def test_batched_uneven_items_round_robin(bpc, unit):
         got = d_.cpu().numpy()
         assert got.tobytes() == want.tobytes(), ("item", i, ds, sx)
     b.close()
+
+
+def test_batched_overlapping_items_rejected_nothing_enqueued():
+    announce("batched cross-item overlap")
+    a = torch.full((64,), 5.0, device="cuda")
+    src = torch.arange(64, dtype=torch.float32, device="cuda")
+    b = api.Batch()
+    # a valid batch is planned first: a rejected call must leave it usable
+    b.apply(L.OP_COPY, [[a[:32], src[:32]]])
+    torch.cuda.synchronize()
+    assert torch.equal(a[:32], src[:32]) and bool((a[32:] == 5.0).all())
+    a.fill_(5.0)
+    torch.cuda.synchronize()
+    # item 1 writes into what item 0 reads (a window of one parent buffer)
+    st = L.triot_apply_batched(
+        L.OP_COPY,
+        [(1, 2, [(16,), (64,)], (16,), [a.data_ptr(), src.data_ptr()], [0, 8]),
+         (1, 2, [(16,), (16,)], None, [src.data_ptr() + 4 * 16, a.data_ptr() + 4 * 32], None)],
+        L.CopyParams(4), b._h, torch.cuda.current_stream().cuda_stream)
+    assert st == L.E_ALIAS
+    with pytest.raises(L.TriotError) as e:
+        b.autotune(L.OP_COPY, [[a[:32], src[:32]], [src[16:48], a[32:]]])
+    assert e.value.status == L.E_ALIAS
+    torch.cuda.synchronize()
+    assert bool((a == 5.0).all())
+    assert torch.equal(src, torch.arange(64, dtype=torch.float32, device="cuda"))
+    # the earlier plan still replays
+    b.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(a[:32], src[:32])
+    b.close()
+
+
+def test_batched_autotune_cfg4_bit_exact():
+    announce("batched autotune cfg4 4096 items")
+    shapes = inputs.cfg4_shapes()
+    xs_np = inputs.cfg4_values(shapes)
+    xs = [torch.from_numpy(x).cuda() for x in xs_np]
+    dsts = [torch.full(inputs.padded_shape(sx, sy), 7.0, device="cuda") for sx, sy in shapes]
+    items = [[d_, x] for d_, x in zip(dsts, xs)]
+    b = api.Batch()
+    default = b.schedule()
+    b.autotune(L.OP_EMBED_FILL, items)
+    tuned = b.schedule()
+    print("default", default, "tuned", tuned)
+    for d_ in dsts:
+        d_.fill_(-2.0)
+    torch.cuda.synchronize()
+    b.apply(L.OP_EMBED_FILL, items)
+    torch.cuda.synchronize()
+    assert b.info()["replayed"] is False
+    _check_items(dsts, xs_np, shapes)
+    # a second handle over new buffers of the same layout picks up the tuned
+    # schedule (same launch grid) and gives the same bits
+    dsts2 = [torch.full(inputs.padded_shape(sx, sy), 9.0, device="cuda") for sx, sy in shapes]
+    b2 = api.Batch()
+    b2.apply(L.OP_EMBED_FILL, [[d_, x] for d_, x in zip(dsts2, xs)])
+    torch.cuda.synchronize()
+    assert b2.info()["blocks"] == b.info()["blocks"]
+    assert b2.info()["units"] == b.info()["units"]
+    _check_items(dsts2, xs_np, shapes)
+    b.close()
+    b2.close()
+    api.tune_reset()
+
+
+def test_batched_autotune_mul_acc_small():
+    announce("batched autotune mul_acc")
+    rng = np.random.default_rng(21)
+    xs, ys, zs, x0 = [], [], [], []
+    for d in range(1, 5):
+        for k in range(6):
+            x_s = tuple(int(v) for v in rng.integers(1, 40, size=d))
+            y_s = tuple(s + int(rng.integers(0, 4)) for s in x_s)
+            z_s = tuple(s + int(rng.integers(0, 4)) for s in x_s)
+            x = rng.standard_normal(x_s).astype(np.float32)
+            xs.append(torch.from_numpy(x).cuda())
+            ys.append(torch.from_numpy(rng.standard_normal(y_s).astype(np.float32)).cuda())
+            zs.append(torch.from_numpy(rng.standard_normal(z_s).astype(np.float32)).cuda())
+            x0.append(x)
+    items = [[x, y, z] for x, y, z in zip(xs, ys, zs)]
+    b = api.Batch()
+    b.autotune(L.OP_MUL_ACC, items)          # runs x += y*z several times
+    for x, x_init in zip(xs, x0):
+        x.copy_(torch.from_numpy(x_init))
+    b.apply(L.OP_MUL_ACC, items)
+    torch.cuda.synchronize()
+    for x, y, z, x_init in zip(xs, ys, zs, x0):
+        w = x_init.copy()
+        yn, zn = y.cpu().numpy(), z.cpu().numpy()
+        oracle.mul_acc(w.shape, w.reshape(-1), w.shape, yn.reshape(-1), yn.shape,
+                       zn.reshape(-1), zn.shape)
+        assert x.cpu().numpy().tobytes() == w.tobytes()
+    b.close()
+    api.tune_reset()
