@@ -210,6 +210,27 @@ triot_status triot_apply(triot_op op, int n_tensors, int d, const int64_t *shape
                          const int64_t *bases, const void *params, void *out,
                          void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as triot_apply, with the same arguments except the workspace,
+ * and the same results bit for bit.  The ops that need a workspace
+ * (MOMENTS, DOT, BBOX, MARGINAL) use instead a scratch array of
+ * TRIOT_NOALLOC_SCRATCH_BYTES that the library holds on each device in
+ * static device memory, from the first call on that device until the
+ * process ends; a problem whose triot_workspace_size() exceeds it returns
+ * TRIOT_E_WORKSPACE and enqueues nothing.  The entry point calls no
+ * hipMalloc, hipFree or other allocating routine.  Nothing in the scratch
+ * needs initialisation (every partial is written before it is read); calls
+ * on one device share its scratch, so calls whose work overlaps in time on
+ * one device (on different streams, or from different threads) race and
+ * give undefined results.  TRIOT_E_DEVICE when the scratch's device
+ * address cannot be obtained. */
+#define TRIOT_NOALLOC_SCRATCH_BYTES (8u << 20)
+triot_status triot_apply_noalloc(triot_op op, int n_tensors, int d, const int64_t *shapes,
+                                 const int64_t *counter_shape, void *const *tensors,
+                                 const int64_t *bases, const void *params, void *out,
+                                 hipStream_t stream);
+
 /* Workspace bytes triot_apply needs for this problem (0 if none). */
 size_t triot_workspace_size(triot_op op, int n_tensors, int d, const int64_t *shapes,
                             const int64_t *counter_shape);

@@ -82,7 +82,9 @@ class TriotError(RuntimeError):
 
 _lib = None
 
-EXPORTS = ["triot_apply", "triot_workspace_size", "triot_batch_create", "triot_batch_destroy",
+NOALLOC_SCRATCH_BYTES = 8 << 20
+
+EXPORTS = ["triot_apply", "triot_apply_noalloc", "triot_workspace_size", "triot_batch_create", "triot_batch_destroy",
            "triot_apply_batched", "triot_batch_launch", "triot_batch_info", "triot_batch_set_schedule",
            "triot_batch_get_schedule", "triot_batch_autotune",
            "triot_autotune", "triot_tune_reset", "triot_schedule_set", "triot_schedule_get",
@@ -103,6 +105,8 @@ def lib():
     pP = ctypes.POINTER(ctypes.c_void_p)
     L.triot_apply.restype = I
     L.triot_apply.argtypes = [I, I, I, pI64, pI64, pP, pI64, P, P, P, SZ, P]
+    L.triot_apply_noalloc.restype = I
+    L.triot_apply_noalloc.argtypes = [I, I, I, pI64, pI64, pP, pI64, P, P, P]
     L.triot_workspace_size.restype = SZ
     L.triot_workspace_size.argtypes = [I, I, I, pI64, pI64]
     L.triot_batch_create.restype = I
@@ -172,6 +176,18 @@ def triot_apply(op, n_tensors, d, shapes, counter_shape, tensors, bases, params,
                              _params_ptr(params), ctypes.c_void_p(int(out) if out else 0),
                              ctypes.c_void_p(int(workspace) if workspace else 0),
                              int(workspace_bytes), ctypes.c_void_p(int(stream) if stream else 0))
+
+
+def triot_apply_noalloc(op, n_tensors, d, shapes, counter_shape, tensors, bases, params,
+                        out, stream) -> int:
+    """Marshal and call triot_apply_noalloc; returns the triot_status."""
+    shapes_a = _i64_array([v for s in shapes for v in s] if d else [])
+    counter_a = _i64_array(counter_shape) if counter_shape is not None else None
+    bases_a = _i64_array(bases) if bases is not None else None
+    return lib().triot_apply_noalloc(int(op), int(n_tensors), int(d), shapes_a, counter_a,
+                                     _ptr_array(tensors), bases_a, _params_ptr(params),
+                                     ctypes.c_void_p(int(out) if out else 0),
+                                     ctypes.c_void_p(int(stream) if stream else 0))
 
 
 def triot_workspace_size(op, n_tensors, d, shapes, counter_shape=None) -> int:

@@ -222,6 +222,63 @@ extern "C" triot_status triot_apply(triot_op op, int n_tensors, int d, const int
     return run_request(r, s, out, workspace, workspace_bytes, stream);
 }
 
+// ---- allocation-free entry point -----------------------------------------
+
+// The scratch of triot_apply_noalloc: per-workgroup partials of the
+// reductions, one copy per device, held until the process ends.  Its name
+// is a host-side stand-in in host code: the device address comes from
+// hipGetSymbolAddress, once per device, and only that address is passed
+// to kernels.
+constexpr size_t kScratchBytes = TRIOT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];    // device address of `scratch` per device id
+}  // namespace
+
+static triot_status scratch_address(void **ptr)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return TRIOT_E_DEVICE;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return TRIOT_E_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return TRIOT_OK;
+}
+
+extern "C" triot_status triot_apply_noalloc(triot_op op, int n_tensors, int d,
+                                            const int64_t *shapes, const int64_t *counter_shape,
+                                            void *const *tensors, const int64_t *bases,
+                                            const void *params, void *out, hipStream_t stream)
+{
+    Request r;
+    triot_status st = validate(op, n_tensors, d, shapes, counter_shape, tensors, bases, params, &r);
+    if (st != TRIOT_OK)
+        return st;
+    if (r.npoints == 0)
+        return TRIOT_OK;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    if (op == TRIOT_OP_MOMENTS || op == TRIOT_OP_DOT || op == TRIOT_OP_BBOX ||
+        op == TRIOT_OP_MARGINAL) {
+        st = scratch_address(&ws);
+        if (st != TRIOT_OK)
+            return st;
+        ws_bytes = kScratchBytes;    // a larger need fails with TRIOT_E_WORKSPACE
+    }
+    Sched s = is_segment_op(op) ? Sched() : sched_for(r);
+    return run_request(r, s, out, ws, ws_bytes, stream);
+}
+
 extern "C" size_t triot_workspace_size(triot_op op, int n_tensors, int d, const int64_t *shapes,
                                        const int64_t *counter_shape)
 {
