@@ -313,15 +313,111 @@ def cpu_baseline(log2_target, threads):
             "threaded": (par[1], par[0], par[2], sum(par_s))}
 
 
-def cpu_model():
+def host_cpus():
+    """CPUs this process may run on (what nproc reports)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def cpu_info():
+    """The host CPU as lscpu and /proc/cpuinfo describe it: model name,
+    family/model/stepping, logical CPUs available, threads per core, clock."""
+    info = {"cpus": host_cpus()}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and "model" not in info:
+                    info["model"] = v
+                elif k == "cpu family" and "family" not in info:
+                    info["family"] = int(v)
+                elif k == "model" and "model_id" not in info:
+                    info["model_id"] = int(v)
+                elif k == "stepping" and "stepping" not in info:
+                    info["stepping"] = v
+                elif k == "cpu MHz" and "mhz" not in info:
+                    info["mhz"] = float(v)
+                elif k == "bogomips" and "bogomips" not in info:
+                    info["bogomips"] = float(v)
+                elif k == "siblings" and "siblings" not in info:
+                    info["siblings"] = int(v)
+                elif k == "cpu cores" and "cores_per_socket" not in info:
+                    info["cores_per_socket"] = int(v)
+    except (OSError, ValueError):
         pass
-    return "unknown"
+    if "siblings" in info and "cores_per_socket" in info and info["cores_per_socket"]:
+        info["threads_per_core"] = info["siblings"] // info["cores_per_socket"]
+    return info
+
+
+def cpu_model():
+    i = cpu_info()
+    s = i.get("model", "unknown CPU")
+    if "family" in i:
+        s += " (family %d model %d stepping %s)" % (i["family"], i.get("model_id", -1),
+                                                    i.get("stepping", "?"))
+    s += ", %d CPUs" % i["cpus"]
+    if "mhz" in i:
+        s += " at %.0f MHz" % i["mhz"]
+    return s
+
+
+def _moment_names(d, cov):
+    names = ["M"] + ["E%d" % i for i in range(d)]
+    if cov:
+        names += ["C%d%d" % (i, j) for i in range(d) for j in range(i, d)]
+    return names
+
+
+def _per_result_error(got32, ref, d, cov):
+    """|g - o| / |o| per result (M, every E_i, every C_ij); an entry whose
+    float64 value is exactly 0 is judged by its absolute error against
+    the scale max(1, max_i C_ii)."""
+    import numpy as np
+    got = np.asarray(got32, dtype=np.float64)
+    n = len(got)
+    ref = np.asarray(ref, dtype=np.float64)[:n]
+    scale = 1.0
+    if cov and d:
+        scale = max(1.0, max(abs(ref[1 + d + i * d - i * (i - 1) // 2]) for i in range(d)))
+    out = {}
+    for name, g, o in zip(_moment_names(d, cov), got, ref):
+        out[name] = abs(g - o) / abs(o) if o != 0 else abs(g - o) / scale
+    return out
+
+
+def moments_errors(dev):
+    """The float32 moments of the library against the float64 oracle, per
+    result: cfg3 (16^6 PMF, M, E and the covariance: 28 results) and the
+    moments step of cfg5's pipeline (the E-based loss reads M and E: 6
+    results), each on the same float32 weights."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1608_00099_amd import api, inputs
+    res = {}
+    p_np = inputs.cfg3_values()
+    p = torch.from_numpy(p_np).to(dev)
+    o32, _ = api.moments(p, cov=True)
+    t0 = time.perf_counter()
+    ref = oracle.moments(inputs.CFG3_SHAPE, [p_np.reshape(-1)], [inputs.CFG3_SHAPE], cov=True)
+    t_or = time.perf_counter() - t0
+    e = _per_result_error(o32.cpu().numpy(), ref, 6, True)
+    res["cfg3_16pow6_cov"] = {"max": max(e.values()), "per_result": e,
+                              "oracle_seconds": round(t_or, 3)}
+    x_np, w_np, _ = inputs.cfg5_values()
+    P = api.pad_embed(torch.from_numpy(x_np).to(dev), inputs.CFG5_P)
+    y = api.mul(P, torch.from_numpy(w_np).to(dev))
+    o32, _ = api.moments(y, cov=False)
+    y_np = y.cpu().numpy()
+    ref = oracle.moments(inputs.CFG5_W, [y_np.reshape(-1)], [inputs.CFG5_W], cov=False)
+    e = _per_result_error(o32.cpu().numpy(), ref, 5, False)
+    res["cfg5_pipeline_first"] = {"max": max(e.values()), "per_result": e}
+    del p, P, y
+    return res
 
 
 # ---------------------------------------------------------------------------
@@ -538,13 +634,24 @@ def _cfg4(dev, out):
     batch.apply(L.OP_EMBED_FILL, items)          # plan, upload, capture, launch
     torch.cuda.synchronize()
     t_plan = (time.perf_counter() - t0) * 1e3
+    t_def = event_ms(batch.launch, reps=20)      # replay, the library's default schedule
+    info_def = dict(batch.info(), schedule=batch.schedule())
+    # the batch autotuner picks the schedule of this batch (cold timing of
+    # the candidates), then the batch is planned and captured again with it
+    t0 = time.perf_counter()
+    batch.autotune(L.OP_EMBED_FILL, items)
+    t_tune = time.perf_counter() - t0
+    batch.apply(L.OP_EMBED_FILL, items)
+    torch.cuda.synchronize()
     t_b = event_ms(batch.launch, reps=20)        # replay of the captured launch
-    info = batch.info()
+    info = dict(batch.info(), schedule=batch.schedule(), tune_seconds=round(t_tune, 2))
     t_pe = event_ms(lambda: [api.embed_fill_(d_, x) for d_, x in zip(dsts, xs)], reps=3, warm=1,
                     cover=False)
     t_pg = graph_ms(lambda: [api.embed_fill_(d_, x) for d_, x in zip(dsts, xs)], reps=5)
     out["cfg4_batched_pad"] = {
-        "batched": dict(t_b, GBs=nb / t_b["median_ms"] / 1e6, first_call_ms=t_plan, **info),
+        "batched": dict(t_b, GBs=nb / t_b["median_ms"] / 1e6, **info),
+        "batched_default_schedule": dict(t_def, GBs=nb / t_def["median_ms"] / 1e6,
+                                         first_call_ms=t_plan, **info_def),
         "plain_per_item_eager": dict(t_pe, GBs=nb / t_pe["median_ms"] / 1e6, launches=len(items)),
         "plain_per_item_graph": dict(t_pg, GBs=nb / t_pg["median_ms"] / 1e6, launches=len(items)),
         "speedup_vs_plain_eager": t_pe["median_ms"] / t_b["median_ms"],
@@ -657,8 +764,9 @@ def main():
                     help="write the schedules the sweep ran with to this JSON file")
     ap.add_argument("--no-tune", action="store_true",
                     help="the library's default schedules (no pinning, no tuning)")
-    ap.add_argument("--cpu-threads", type=int, default=16,
-                    help="threads of the threaded CPU oracle timing (at most the CPUs present)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the threaded CPU oracle timing (default: every CPU this "
+                         "process may use, as nproc reports)")
     ap.add_argument("--cpu-log2", type=float, default=26,
                     help="log2 elements per tensor of the CPU oracle sample")
     args = ap.parse_args()
@@ -739,7 +847,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        threads = host_cpus() if args.cpu_threads <= 0 else max(1, min(args.cpu_threads,
+                                                                         host_cpus()))
         log("CPU oracle baseline (2^%g elements per tensor, 1 and %d threads)"
             % (args.cpu_log2, threads))
         r = cpu_baseline(args.cpu_log2, threads)
@@ -752,7 +861,10 @@ def main():
                          "all)" % (args.cpu_log2, cpu_model(), threads, secs_t),
                "min": round(lo, 3), "max": round(hi, 3),
                "single_thread": {"value": round(gbs1, 3), "cores": 1,
-                                 "seconds": round(secs1, 2)}}
+                                 "seconds": round(secs1, 2)},
+               "host": cpu_info()}
+        log("moments per-result error against the float64 oracle")
+        cpu["moments_error"] = moments_errors(dev)
 
     ext = None
     if not args.no_extras:

@@ -131,20 +131,57 @@ __device__ __forceinline__ int64_t row_offset(const SegPlan &P, int k, const uin
     return off;
 }
 
-// Sum over the 32 lanes of a half wave (butterfly; every lane gets it).
+// Cross-lane sums by DPP (data-parallel primitives: an operand read from
+// another lane of the same row of 16 inside the ALU instruction, no LDS
+// traffic).  A float64 moves as its two 32-bit halves through the same lane
+// pattern; lanes of rows outside ROWS receive +0.0.
+template <int CTRL, int ROWS> __device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xF, false);
+    const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xF, false);
+    return __hiloint2double(h2, l2);
+}
+
+enum : int {
+    DPP_QUAD_XOR1 = 0xB1,      // quad_perm [1,0,3,2]
+    DPP_QUAD_XOR2 = 0x4E,      // quad_perm [2,3,0,1]
+    DPP_ROW_MIRROR = 0x140,    // lane i of a row of 16 reads lane 15 - i
+    DPP_HALF_MIRROR = 0x141,   // lane i of a half row of 8 reads lane 7 - i
+    DPP_ROW_BCAST15 = 0x142,   // lane 15 of each row to every lane of the next row
+    DPP_ROW_BCAST31 = 0x143,   // lane 31 to every lane of rows 2 and 3
+};
+
+// Every lane of each row of 16 gets the sum of its row's 16 values.
+__device__ __forceinline__ double row16_sum(double v)
+{
+    v += dpp_f64<DPP_QUAD_XOR1, 0xF>(v);
+    v += dpp_f64<DPP_QUAD_XOR2, 0xF>(v);
+    v += dpp_f64<DPP_HALF_MIRROR, 0xF>(v);
+    v += dpp_f64<DPP_ROW_MIRROR, 0xF>(v);
+    return v;
+}
+
+// Sum over the 32 lanes of each half wave; the sum is valid in the half
+// wave's LAST lane (31 or 63).  Fixed order: deterministic.
 __device__ __forceinline__ double half_wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 16; o >= 1; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
+    v = row16_sum(v);
+    return v + dpp_f64<DPP_ROW_BCAST15, 0xA>(v);    // rows 1 and 3 add rows 0 and 2
+}
+
+// Sum over the 64 lanes of a wave, valid in lane 63.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v = half_wave_sum(v);
+    return v + dpp_f64<DPP_ROW_BCAST31, 0xC>(v);    // rows 2 and 3 add lane 31
 }
 
 // Workgroup sum of the per-thread terms acc[0..T) into dst[0..T), in a
 // fixed order.  Eight terms at a time pass through LDS transposed: thread t
 // stores its eight values at x[q][t]; then the 32 threads of half wave q sum
 // term q, each over eight stored values, and the half wave folds its 32
-// sums by shuffles.  A butterfly over all 64 lanes per term instead would
+// sums by DPP.  A butterfly over all 64 lanes per term instead would
 // cost each wave 12 cross-lane reads per term, and those all queue on the
 // CU's one LDS unit.
 template <int T>
@@ -168,7 +205,7 @@ __device__ __forceinline__ void block_sums(const double *acc, double (*x)[NT], d
                 v += x[q][k * 32 + part];
         }
         v = half_wave_sum(v);
-        if (part == 0 && i0 + q < T)
+        if (part == 31 && i0 + q < T)
             dst[i0 + q] = v;
     }
     __syncthreads();
@@ -424,97 +461,105 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
         partials[(size_t)i * nb + blockIdx.x] = tot[i];
 }
 
-// Combines the per-workgroup partials of moments_kernel and writes [M, E, C]
-// in the caller's layout.  One workgroup of FNT threads, launched right
-// after the main pass on the same stream (the kernel boundary makes every
-// partial visible; no device-wide fence per workgroup).  The threads form
-// 32 term slots of 32 lanes: lane l of a slot adds the partials of blocks
-// l, l + 32, ... of its term (loads issued together, in batches), then the
-// slot's half wave folds its 32 sums by shuffles.  Fixed order throughout:
-// deterministic.
+// Combines the per-workgroup partials of moments_kernel into the caller's
+// layout [M, E, C]: one wavefront per output value, launched right after
+// the main pass on the same stream (the kernel boundary makes every partial
+// visible; no device-wide fence per workgroup).  Output o needs at most
+// four terms (M; K_p for E_i; K_p, K_q and C_pq for C_ij): lane l adds the
+// partials of blocks l, l + 64, .. of each, all loads of a pass in flight
+// together, then the wave folds its 64 sums by DPP.  Fixed order
+// throughout: deterministic.
+constexpr int ONT = 64;
+// Threads of the one-workgroup combines (inner product, bounding box).
 constexpr int FNT = 1024;
 
 template <int DM, bool COV>
-__global__ __launch_bounds__(FNT) void moments_final_kernel(const SegPlan P)
+__global__ __launch_bounds__(ONT) void moments_out_kernel(const SegPlan P)
 {
     typedef Terms<DM, COV> TT;
-    constexpr int T = TT::T;
-    constexpr int SLOTS = FNT / 32;
-    constexpr int BATCH = 16;            // loads in flight per thread
-    __shared__ double tot[T];
-    __shared__ int pos_of[MAXD];
     const int D = (int)P.D;
+    const int d = (int)P.d_orig;
+    const int o = blockIdx.x;
+    const int lane = threadIdx.x;
+    // position (accumulator index) of original axis i, -1 when dropped
+    auto pos_of = [&](int i) -> int {
+        for (int p = 0; p < D; ++p)
+            if ((int)P.orig[D - 1 - p] == i)
+                return p;
+        return -1;
+    };
+    int term[4] = {0, 0, 0, 0};
+    int nt = 1;                // terms this output reads (term[0] is M)
+    int p = -1, q = -1;
+    bool dropped = false;      // a dropped axis: the plain definition's 0/M
+    if (o >= 1 && o <= d) {
+        p = pos_of(o - 1);
+        if (p < 0) {
+            dropped = true;
+        } else {
+            term[1] = TT::K + p;
+            nt = 2;
+        }
+    } else if (o > d) {
+        // o -> (i, j), i <= j, in the row-major upper triangle
+        int r = o - 1 - d, i = 0;
+        while (r >= d - i) {
+            r -= d - i;
+            ++i;
+        }
+        const int j = i + r;
+        p = pos_of(i);
+        q = pos_of(j);
+        if (p < 0 || q < 0 || !COV) {
+            dropped = true;
+        } else {
+            term[1] = TT::K + p;
+            term[2] = TT::K + q;
+            term[3] = TT::c(p < q ? p : q, p < q ? q : p);
+            nt = 4;
+        }
+    }
     const GLOBAL double *partials = (const GLOBAL double *)((uintptr_t)P.ws + 256);
     const uint32_t nb = P.nblocks;
-    const int slot = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    constexpr int BATCH = 8;             // loads in flight per term and thread
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b0 = 0; b0 < nb; b0 += ONT * BATCH) {
+        double x[4][BATCH];
 #pragma unroll
-    for (int i0 = 0; i0 < T; i0 += SLOTS) {
-        const int i = i0 + slot;
-        double v = 0.0;
-        if (i < T) {
-            const GLOBAL double *row = partials + (size_t)i * nb;
-            for (uint32_t b0 = 0; b0 < nb; b0 += 32 * BATCH) {
-                double x[BATCH];
+        for (int k = 0; k < 4; ++k) {
+            const GLOBAL double *row = partials + (size_t)term[k] * nb;
 #pragma unroll
-                for (int k = 0; k < BATCH; ++k) {
-                    const uint32_t b = b0 + (uint32_t)(k * 32 + lane);
-                    x[k] = row[b < nb ? b : 0u];
-                }
-#pragma unroll
-                for (int k = 0; k < BATCH; ++k)
-                    v += (b0 + (uint32_t)(k * 32 + lane) < nb) ? x[k] : 0.0;
+            for (int c = 0; c < BATCH; ++c) {
+                const uint32_t b = b0 + (uint32_t)(c * ONT + lane);
+                x[k][c] = (k < nt) ? row[b < nb ? b : 0u] : 0.0;
             }
         }
-        v = half_wave_sum(v);
-        if (lane == 0 && i < T)
-            tot[i] = v;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < BATCH; ++c)
+                s[k] += (b0 + (uint32_t)(c * ONT + lane) < nb) ? x[k][c] : 0.0;
     }
-    if (threadIdx.x < MAXD)
-        pos_of[threadIdx.x] = -1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int p = 0; p < D; ++p) {
-            uint32_t o = P.orig[D - 1 - p];
-            if (o != 0xFFFFFFFFu)
-                pos_of[o] = p;
-        }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        s[k] = wave_sum(s[k]);
+    if (lane != ONT - 1)
+        return;
+    const double M = s[0];
+    double v;
+    if (o == 0) {
+        v = M;
+    } else if (dropped) {
+        v = 0.0 / M;
+    } else if (o <= d) {
+        v = P.center[D - 1 - p] + s[1] / M;
+    } else {
+        const double ei = s[1] / M, ej = s[2] / M;
+        v = s[3] / M - ei * ej;
     }
-    __syncthreads();
-    const int d = (int)P.d_orig;
-    const bool cov = (P.flags & TRIOT_MOMENTS_COV) != 0;
-    const int nout = 1 + d + (cov ? d * (d + 1) / 2 : 0);
-    const double M = tot[0];
-    float *out32 = (float *)(uintptr_t)P.out32;
-    double *out64 = (double *)(uintptr_t)P.out64;
-    for (int o = threadIdx.x; o < nout; o += FNT) {
-        double v;
-        if (o == 0) {
-            v = M;
-        } else if (o <= d) {
-            const int i = o - 1;
-            const int p = pos_of[i];
-            v = (p < 0) ? 0.0 / M : P.center[D - 1 - p] + tot[TT::K + p] / M;
-        } else {
-            // o -> (i, j), i <= j, in the row-major upper triangle
-            int r = o - 1 - d, i = 0;
-            while (r >= d - i) {
-                r -= d - i;
-                ++i;
-            }
-            const int j = i + r;
-            const int p = pos_of[i], q = pos_of[j];
-            if (p < 0 || q < 0) {
-                v = 0.0 / M;
-            } else {
-                const int lo = p < q ? p : q, hi = p < q ? q : p;
-                const double ei = tot[TT::K + p] / M, ej = tot[TT::K + q] / M;
-                v = COV ? tot[TT::c(lo, hi)] / M - ei * ej : 0.0;
-            }
-        }
-        out32[o] = (float)v;
-        if (out64)
-            out64[o] = v;
-    }
+    ((float *)(uintptr_t)P.out32)[o] = (float)v;
+    if (P.out64)
+        ((double *)(uintptr_t)P.out64)[o] = v;
 }
 
 // ---------------------------------------------------------------------
@@ -704,7 +749,7 @@ __global__ __launch_bounds__(FNT) void dot_final_kernel(const SegPlan P)
     for (uint32_t b = threadIdx.x; b < nb; b += FNT)
         v += partials[b];
     v = half_wave_sum(v);
-    if ((threadIdx.x & 31) == 0)
+    if ((threadIdx.x & 31) == 31)
         hw[threadIdx.x >> 5] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -952,7 +997,9 @@ static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
     case 1: hipLaunchKernelGGL((moments_kernel<DM, COV, false, false, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
     default: hipLaunchKernelGGL((moments_kernel<DM, COV, false, false, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
     }
-    hipLaunchKernelGGL((moments_final_kernel<DM, COV>), dim3(1), dim3(FNT), 0, st, L.plan);
+    const int d = (int)L.plan.d_orig;
+    const int nout = 1 + d + (COV ? d * (d + 1) / 2 : 0);
+    hipLaunchKernelGGL((moments_out_kernel<DM, COV>), dim3(nout), dim3(ONT), 0, st, L.plan);
     return hipGetLastError();
 }
 

@@ -327,7 +327,14 @@ def test_moments_cfg3_full_size():
     shape = inputs.CFG3_SHAPE
     want = oracle.moments(shape, [p.reshape(-1)], [shape], cov=True)
     o32, o64 = api.moments(dev(p), cov=True)
-    e = _check_moments(host(o32), host(o64), want, 6, True)
+    g32 = host(o32)
+    # the error of every one of the 28 results, reported before the check
+    names = ["M"] + ["E%d" % i for i in range(6)] + ["C%d%d" % (i, j) for i in range(6)
+                                                    for j in range(i, 6)]
+    per = {nm: abs(float(g) - w) / abs(w) for nm, g, w in zip(names, g32, want)}
+    print("cfg3 per-result relative error of the float32 results:",
+          " ".join("%s=%.2e" % kv for kv in per.items()), flush=True)
+    e = _check_moments(g32, host(o64), want, 6, True)
     print("cfg3 max relative error (float32 results):", e)
 
 
