@@ -70,6 +70,18 @@ template <class T, int CP> __device__ __forceinline__ void gstore(gchar *p, uint
 // Store of a ragged row's last vector: only its words from `skip` on are
 // new (the others belong to the vector before it, stored by another lane).
 // 1 <= skip < V.
+//
+// whole_tail: the read-modify-write ops (x += y*z, out = a*b in place,
+// benchmark 3's update) store the last vector whole when the vector before
+// it belongs to the previous lane of the same wavefront: both then sit in
+// the same load and store instructions of one step, a wavefront issues all
+// of a step's loads before its stores, so the shared words were loaded
+// unchanged by both lanes and both store the same bits there.  The first
+// lane of a wavefront (its predecessor belongs to another wavefront, which
+// may already have stored) keeps the word-wise store.  A whole store is
+// part of the same store instruction as its predecessor's and the two fill
+// their cache lines together, where word stores issued after it reach
+// memory as separate partial writes.
 template <class T, int CP>
 __device__ __forceinline__ void gstore_tail(gchar *p, uint32_t off, T v, uint32_t skip)
 {
@@ -420,7 +432,9 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
             for (int u = 0; u < U; ++u)
                 if (valid[u]) {
                     VF prod = y[u] * z[u];       // rounded once (no contraction)
-                    if (tl[u])
+                    if (tl[u] && (threadIdx.x & 63u) != 0)
+                        gstore<VF, CP>(bp[0], off[0][u], x[u] + prod);   // see whole_tail
+                    else if (tl[u])
                         gstore_tail<VF, CP>(bp[0], off[0][u], x[u] + prod, P.tskip);
                     else
                         gstore<VF, CP>(bp[0], off[0][u], x[u] + prod);
@@ -440,7 +454,9 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
                     // (x + y*x) - z, each operation rounded once
                     VF prod = y[u] * x[u];
                     VF sum = x[u] + prod;
-                    if (tl[u])
+                    if (tl[u] && (threadIdx.x & 63u) != 0)
+                        gstore<VF, CP>(bp[0], off[0][u], sum - z[u]);     // see whole_tail
+                    else if (tl[u])
                         gstore_tail<VF, CP>(bp[0], off[0][u], sum - z[u], P.tskip);
                     else
                         gstore<VF, CP>(bp[0], off[0][u], sum - z[u]);
@@ -456,9 +472,10 @@ __device__ __forceinline__ void run_unit(const CoPlan &P, uint32_t unit, const R
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (valid[u]) {
-                    // x may be y or z (in place): the shared words are not
-                    // stored twice
-                    if (tl[u])
+                    // x may be y or z (in place)
+                    if (tl[u] && (threadIdx.x & 63u) != 0)
+                        gstore<VF, CP>(bp[0], off[0][u], a[u] * b[u]);    // see whole_tail
+                    else if (tl[u])
                         gstore_tail<VF, CP>(bp[0], off[0][u], a[u] * b[u], P.tskip);
                     else
                         gstore<VF, CP>(bp[0], off[0][u], a[u] * b[u]);
