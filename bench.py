@@ -450,6 +450,20 @@ def event_ms(fn, reps=10, warm=2, pre=None, cover=True):
     return {"median_ms": ms[len(ms) // 2], "min_ms": ms[0], "max_ms": ms[-1]}
 
 
+def wall_ms(fn, n=20):
+    """Host wall time per call of fn over n back-to-back calls (the device
+    drained before and after): what a loop calling fn sustains, enqueue
+    overhead included."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / n * 1e3
+
+
 def graph_ms(fn, reps=10):
     """GPU time of fn's launches captured once in a torch CUDA graph and
     replayed (no host work between the kernels)."""
@@ -698,7 +712,8 @@ def _cfg5(dev, out):
 
     t_raw = event_ms(raw, reps=10)
 
-    # the same step with forward and backward captured as graphs
+    # the same step, forward and backward captured as one graph over the
+    # leaf tensors themselves (no static-input copies) and replayed
     xg, wg = xd.clone().requires_grad_(True), wd.clone().requires_grad_(True)
 
     def step(a, b):
@@ -707,14 +722,12 @@ def _cfg5(dev, out):
         M, E, C = autograd.moments(y)
         return (lam * E).sum()
 
-    g_step = torch.cuda.make_graphed_callables(step, (xg, wg))
-
-    def graphed():
-        xg.grad = None
-        wg.grad = None
-        g_step(xg, wg).backward()
-
-    t_graph = event_ms(graphed, reps=10)
+    cap = autograd.CapturedStep(step, (xg, wg))
+    t_graph = event_ms(cap.replay, reps=10)
+    t_graph["wall_ms_per_step"] = wall_ms(cap.replay)
+    t_auto["wall_ms_per_step"] = wall_ms(fwd_bwd)
+    t_raw["wall_ms_per_step"] = wall_ms(raw)
+    del cap
     fwd_bytes = (4 * prod(inputs.CFG5_P) + 4 * prod(inputs.CFG5_X) + 12 * prod(inputs.CFG5_W)
                  + 4 * prod(inputs.CFG5_W))
     bwd_bytes = (4 * prod(inputs.CFG5_W) + 20 * prod(inputs.CFG5_W)

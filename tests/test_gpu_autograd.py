@@ -132,3 +132,75 @@ def test_pipeline_in_captured_graphs_matches_eager():
         got = (loss.detach().cpu().numpy(), xg.grad.cpu().numpy(), wg.grad.cpu().numpy())
         for a, b in zip(got, ref):
             assert a.tobytes() == b.tobytes(), rep
+
+
+def test_pipeline_captured_as_one_graph_matches_eager():
+    """Forward and backward of the pipeline captured as ONE graph over the
+    leaf tensors (autograd.CapturedStep) and replayed, with eager work,
+    in-place input updates and synchronisation between replays: every
+    replay gives the eager loss and gradients bit for bit."""
+    announce("autograd cfg5 one captured step")
+    x_np, w_np, lam = inputs.cfg5_values()
+    lam_t = torch.from_numpy(lam.astype(np.float32)).cuda()
+
+    def step(x, w):
+        P = autograd.pad_embed(x, inputs.CFG5_P)
+        y = autograd.mul(P, w)
+        M, E, C = autograd.moments(y)
+        return (lam_t * E).sum()
+
+    def eager(xv, wv):
+        x = torch.from_numpy(xv).cuda().requires_grad_(True)
+        w = torch.from_numpy(wv).cuda().requires_grad_(True)
+        loss = step(x, w)
+        loss.backward()
+        torch.cuda.synchronize()
+        return loss.detach().cpu().numpy(), x.grad.cpu().numpy(), w.grad.cpu().numpy()
+
+    xg = torch.from_numpy(x_np).cuda().requires_grad_(True)
+    wg = torch.from_numpy(w_np).cuda().requires_grad_(True)
+    cap = autograd.CapturedStep(step, (xg, wg))
+    for rep in range(3):
+        xv = (x_np * (1.0 + 0.25 * rep)).astype(np.float32)   # new values, written in place
+        with torch.no_grad():
+            xg.copy_(torch.from_numpy(xv))
+        other = torch.arange(4096, device="cuda", dtype=torch.float32)
+        assert float(other.sum()) == 4096 * 4095 / 2           # eager work, synchronised
+        loss = cap.replay()
+        torch.cuda.synchronize()
+        got = (loss.detach().cpu().numpy(), xg.grad.cpu().numpy(), wg.grad.cpu().numpy())
+        ref = eager(xv, w_np)
+        for a, b in zip(got, ref):
+            assert a.tobytes() == b.tobytes(), rep
+
+
+def test_moments_backward_unused_outputs():
+    """Only E used, only M used, and E and C used: the gradient equals the
+    adjoint kernel on the partials with zeros where an output is unused."""
+    announce("moments backward partial use")
+    rng = np.random.default_rng(17)
+    shape = (5, 6, 7)
+    pn = rng.random(shape).astype(np.float32)
+    for use in ("E", "M", "EC"):
+        p = torch.from_numpy(pn).cuda().requires_grad_(True)
+        cov = "C" in use
+        M, E, C = autograd.moments(p, cov=cov)
+        loss = 0.0
+        if "M" in use:
+            loss = loss + 3.0 * M.sum()
+        if "E" in use:
+            loss = loss + (torch.arange(1, 4, device="cuda", dtype=torch.float32) * E).sum()
+        if "C" in use:
+            loss = loss + (0.5 * C).sum()
+        loss.backward()
+        o32, o64 = api.moments(p.detach(), cov=cov)
+        n = 1 + 3 + (6 if cov else 0)
+        gm = torch.zeros(n, device="cuda")
+        if "M" in use:
+            gm[0] = 3.0
+        if "E" in use:
+            gm[1:4] = torch.arange(1, 4, device="cuda", dtype=torch.float32)
+        if "C" in use:
+            gm[4:] = 0.5
+        g = api.moments_adj(shape, o64, gm, cov=cov)
+        assert torch.equal(p.grad, g), use
