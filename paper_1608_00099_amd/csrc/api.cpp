@@ -761,12 +761,18 @@ static std::string batch_key(triot_op op, int elem_bytes, const std::vector<Requ
 }
 
 // Plans of the items with points, their first work units and the rows of
-// the largest multi-row box.
+// the largest multi-row box.  `table` is what goes to the device: the
+// nitems + 1 first units, then (batches of at most kUnitTableMax units) the
+// item of every unit, so that a workgroup finds a unit's item with one load.
+constexpr uint64_t kUnitTableMax = uint64_t(1) << 22;
+
 struct BatchPlan {
     std::vector<CoPlan> plans;
     std::vector<uint32_t> ustart;
+    std::vector<uint32_t> table;
     uint64_t total = 0;
     uint32_t rows_max = 0;
+    bool has_uitem() const { return table.size() > ustart.size(); }
 };
 
 static triot_status batch_plan(const std::vector<Request> &reqs, const Sched &s, int cus,
@@ -794,6 +800,13 @@ static triot_status batch_plan(const std::vector<Request> &reqs, const Sched &s,
             return TRIOT_E_UNSUPPORTED;
         bp->ustart.push_back((uint32_t)bp->total);
     }
+    bp->table = bp->ustart;
+    if (bp->total <= kUnitTableMax) {
+        bp->table.reserve(bp->ustart.size() + bp->total);
+        for (size_t i = 0; i + 1 < bp->ustart.size(); ++i)
+            for (uint32_t u = bp->ustart[i]; u < bp->ustart[i + 1]; ++u)
+                bp->table.push_back((uint32_t)i);
+    }
     return TRIOT_OK;
 }
 
@@ -812,6 +825,7 @@ static BatchLaunch batch_launch_args(triot_op op, const BatchPlan &bp, const Sch
     BatchLaunch B;
     B.plans = d_plans;
     B.ustart = d_ustart;
+    B.uitem = bp.has_uitem() ? d_ustart + bp.ustart.size() : nullptr;
     B.nitems = (uint32_t)bp.plans.size();
     B.total = (uint32_t)bp.total;
     B.rows_max = bp.rows_max;
@@ -1003,13 +1017,13 @@ extern "C" triot_status triot_apply_batched(triot_op op, int n_items, const trio
     handle->blocks = batch_grid(bp, s, cus);
 
     if (hipMalloc((void **)&handle->d_plans, bp.plans.size() * sizeof(CoPlan)) != hipSuccess ||
-        hipMalloc((void **)&handle->d_ustart, bp.ustart.size() * sizeof(uint32_t)) != hipSuccess) {
+        hipMalloc((void **)&handle->d_ustart, bp.table.size() * sizeof(uint32_t)) != hipSuccess) {
         batch_release(handle);
         return TRIOT_E_DEVICE;
     }
     if (hipMemcpy(handle->d_plans, bp.plans.data(), bp.plans.size() * sizeof(CoPlan),
                   hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(handle->d_ustart, bp.ustart.data(), bp.ustart.size() * sizeof(uint32_t),
+        hipMemcpy(handle->d_ustart, bp.table.data(), bp.table.size() * sizeof(uint32_t),
                   hipMemcpyHostToDevice) != hipSuccess) {
         batch_release(handle);
         return TRIOT_E_DEVICE;
@@ -1062,8 +1076,8 @@ extern "C" triot_status triot_batch_autotune(triot_batch *handle, triot_op op, i
         return st;
     const int cus = device_cus();
     const std::string key = batch_key(op, batch_elem_bytes(op, params), reqs);
-    // Device tables sized once: the plan count and unit starts do not
-    // depend on the schedule (items with points, one plan each).
+    // Device tables: the plan count does not depend on the schedule (items
+    // with points, one plan each); the unit table grows with smaller units.
     BatchPlan bp;
     st = batch_plan(reqs, batch_default_sched(), cus, &bp);
     if (st != TRIOT_OK)
@@ -1072,6 +1086,7 @@ extern "C" triot_status triot_batch_autotune(triot_batch *handle, triot_op op, i
         return TRIOT_OK;   // nothing to time
     CoPlan *d_plans = nullptr;
     uint32_t *d_ustart = nullptr;
+    size_t table_cap = bp.table.size();
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     auto cleanup = [&]() {
         if (d_plans)
@@ -1084,7 +1099,7 @@ extern "C" triot_status triot_batch_autotune(triot_batch *handle, triot_op op, i
             (void)hipEventDestroy(ev1);
     };
     if (hipMalloc((void **)&d_plans, bp.plans.size() * sizeof(CoPlan)) != hipSuccess ||
-        hipMalloc((void **)&d_ustart, bp.ustart.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&d_ustart, table_cap * sizeof(uint32_t)) != hipSuccess ||
         hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess) {
         cleanup();
         return TRIOT_E_DEVICE;
@@ -1100,9 +1115,18 @@ extern "C" triot_status triot_batch_autotune(triot_batch *handle, triot_op op, i
             return t;
         if (p.plans.size() != bp.plans.size())
             return TRIOT_E_DEVICE;     // cannot happen: one plan per item with points
+        if (p.table.size() > table_cap) {
+            // smaller units: a longer unit table (the previous candidate's
+            // launches are done: time_it ends with a stream synchronise)
+            (void)hipFree(d_ustart);
+            d_ustart = nullptr;
+            if (hipMalloc((void **)&d_ustart, p.table.size() * sizeof(uint32_t)) != hipSuccess)
+                return TRIOT_E_DEVICE;
+            table_cap = p.table.size();
+        }
         if (hipMemcpyAsync(d_plans, p.plans.data(), p.plans.size() * sizeof(CoPlan),
                            hipMemcpyHostToDevice, stream) != hipSuccess ||
-            hipMemcpyAsync(d_ustart, p.ustart.data(), p.ustart.size() * sizeof(uint32_t),
+            hipMemcpyAsync(d_ustart, p.table.data(), p.table.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice, stream) != hipSuccess)
             return TRIOT_E_DEVICE;
         BatchLaunch B = batch_launch_args(op, p, s, cus, d_plans, d_ustart);

@@ -560,6 +560,7 @@ __global__ __launch_bounds__(NT) void coiter_kernel(const CoPlan P)
 template <int OP, int U, int CP>
 __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ plans,
                                                      const uint32_t *__restrict__ ustart,
+                                                     const uint32_t *__restrict__ uitem,
                                                      uint32_t nitems, uint32_t total, uint32_t rr)
 {
     const uint32_t lb = logical_block();
@@ -580,17 +581,22 @@ __global__ __launch_bounds__(NT) void batched_kernel(const CoPlan *__restrict__ 
     uint32_t item = 0, first = 0, next = 0;    // next == 0: nothing loaded yet
     for (; u < uend; u += step) {
         if (u >= next) {
-            // the item holding u: the last one whose first unit is <= u
-            // (empty items share their first unit with the next item)
-            uint32_t lo = item, hi = nitems;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (ustart[mid] <= u)
-                    lo = mid;
-                else
-                    hi = mid;
+            // the item holding u: one load from the unit table, else the
+            // last item whose first unit is <= u (binary search; empty items
+            // share their first unit with the next item)
+            if (uitem) {
+                item = uitem[u];
+            } else {
+                uint32_t lo = item, hi = nitems;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (ustart[mid] <= u)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                item = lo;
             }
-            item = lo;
             first = ustart[item];
             next = ustart[item + 1];
             __syncthreads();
@@ -747,8 +753,8 @@ static void go_batched(BatchLaunch &B, hipStream_t st)
     const size_t lds = (size_t)B.rows_max * (OpInfo<OP>::N + (OpInfo<OP>::PRED ? 1 : 0)) * 4u;
     B.launched = clamp_resident(
         B.blocks, resident_per_cu(reinterpret_cast<const void *>(kern), lds, occ), B.cus);
-    hipLaunchKernelGGL(kern, dim3(B.launched), dim3(NT), lds, st, B.plans, B.ustart, B.nitems,
-                       B.total, B.rr);
+    hipLaunchKernelGGL(kern, dim3(B.launched), dim3(NT), lds, st, B.plans, B.ustart, B.uitem,
+                       B.nitems, B.total, B.rr);
 }
 
 template <int OP>

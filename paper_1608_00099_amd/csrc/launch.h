@@ -12,6 +12,8 @@ hipError_t launch_coiter(int co_op, const CoLaunch &L, hipStream_t st);
 struct BatchLaunch {
     const CoPlan *plans;      // device: the item plans
     const uint32_t *ustart;   // device: each item's first work unit, then the total
+    const uint32_t *uitem;    // device: the item of every work unit, or null (then
+                              // the kernel searches ustart)
     uint32_t nitems;
     uint32_t total;           // work units over all items
     uint32_t rows_max;        // largest rows per box among items with RB > 1 (0: none)
