@@ -585,11 +585,18 @@ def _fftconv(dev, out):
     y = torch.rand((B,) + sy, device=dev)
     s = fftconv.conv_shape(sx, sy)
     n = tuple(fftconv.good_size(v) for v in s)
+    # the library's autotuner on the two pads and the crop
+    from paper_1608_00099_amd import _lib as L
+    full = torch.empty((B,) + n, device=dev)
+    cropped = torch.empty((B,) + s, device=dev)
+    api.autotune(L.OP_EMBED_FILL, [full, x], params=L.CopyParams(4))
+    api.autotune(L.OP_EMBED_FILL, [full, y], params=L.CopyParams(4))
+    api.autotune(L.OP_COPY, [cropped, full], counter=(B,) + s, params=L.CopyParams(4))
+    del cropped
     fftconv.fft_conv(x, y, batch_dims=1)          # plans the transforms
     t_all = event_ms(lambda: fftconv.fft_conv(x, y, batch_dims=1), reps=10)
     xp = api.pad_embed(x, (B,) + n)
     yp = api.pad_embed(y, (B,) + n)
-    full = torch.empty((B,) + n, device=dev)
     t_pad = event_ms(lambda: (api.pad_embed(x, (B,) + n), api.pad_embed(y, (B,) + n)), reps=10)
     t_crop = event_ms(lambda: api.crop(full, (B,) + s), reps=10)
     pad_bytes = 4 * B * (prod(sx) + prod(sy) + 2 * prod(n))
@@ -676,6 +683,33 @@ def _cfg4(dev, out):
     log("batched done")
 
 
+def _tune_cfg5(dev, xd, wd):
+    """The library's autotuner on each element-wise launch of the pipeline
+    (pad-embed, product, product adjoint, crop), on buffers of the
+    pipeline's shapes: every later call with the same shapes (the raw,
+    autograd and graphed steps below) runs with the tuned schedule.  The
+    moments kernels have one schedule."""
+    import torch
+    from paper_1608_00099_amd import api, inputs
+    from paper_1608_00099_amd import _lib as L
+    P = torch.empty(inputs.CFG5_P, device=dev)
+    y = torch.empty(inputs.CFG5_W, device=dev)
+    gy = torch.rand(inputs.CFG5_W, device=dev)
+    ga = torch.empty_like(P)
+    gb = torch.empty_like(wd)
+    gx = torch.empty_like(xd)
+    probs = {"pad_embed": (L.OP_EMBED_FILL, [P, xd], dict(params=L.CopyParams(4))),
+             "mul": (L.OP_MUL, [y, P, wd], dict(counter=inputs.CFG5_W)),
+             "mul_adj": (L.OP_MUL_ADJ, [ga, gb, gy, P, wd], {}),
+             "crop": (L.OP_COPY, [gx, ga], dict(counter=inputs.CFG5_X, params=L.CopyParams(4)))}
+    out = {}
+    for name, (op, ts, kw) in probs.items():
+        api.autotune(op, ts, **kw)
+        out[name] = api.schedule_get(op, ts, **kw)
+    del P, y, gy, ga, gb, gx
+    return out
+
+
 def _cfg5(dev, out):
     import numpy as np
     import torch
@@ -685,6 +719,7 @@ def _cfg5(dev, out):
     x = torch.from_numpy(x_np).to(dev).requires_grad_(True)
     w = torch.from_numpy(w_np).to(dev).requires_grad_(True)
     lam = torch.from_numpy(lam_np.astype(np.float32)).to(dev)
+    tuned = _tune_cfg5(dev, x.detach(), w.detach())
 
     def fwd_bwd():
         # a fresh step: gradients set to None, as optimizers' zero_grad does,
@@ -737,7 +772,7 @@ def _cfg5(dev, out):
                             "autograd_over_raw": t_auto["median_ms"] / t_raw["median_ms"],
                             "graphed_over_raw": t_graph["median_ms"] / t_raw["median_ms"],
                             "GBs_raw": (fwd_bytes + bwd_bytes) / t_raw["median_ms"] / 1e6,
-                            "bytes": fwd_bytes + bwd_bytes}
+                            "bytes": fwd_bytes + bwd_bytes, "schedules": tuned}
     log("autograd done")
 
 
