@@ -44,7 +44,16 @@ __device__ __forceinline__ uint32_t seg_logical_block()
     return b;
 }
 
+// The 32-axis instances of the row kernels read their plan in place, from
+// the kernel-argument segment (explicit arguments start at its offset 0):
+// a by-value aggregate parameter indexed at run time (the axis tables) is
+// otherwise copied to per-lane scratch memory first, which the compiler
+// does for those larger instances.
+#define SEG_PLAN_FOR(DM) \
+    const SegPlan &P = (DM) > 8 ? *(const SegPlan *)__builtin_amdgcn_kernarg_segment_ptr() : plan
+
 #define GLOBAL __attribute__((address_space(1)))
+#define SHARED __attribute__((address_space(3)))
 
 // LDS staging: one padding word every 32 words keeps the per-thread segment
 // reads (stride L words across lanes) spread over the banks.
@@ -355,6 +364,145 @@ __device__ __forceinline__ void seg_moments(const SegPlan &P, const int64_t off[
     }
 }
 
+// Staged tile loads (plan flag `stage`: every operand contiguous over the
+// counter, rows of L = 4, 8 or 16 words, so G == 1 and a wave's 64
+// segments are one range of 64 L consecutive words).  Per-lane segment
+// loads put 64 lanes on 64 different 64-byte pieces in every instruction:
+// the L1 sends each piece to L2 as a request of its own, and on MI355X the
+// address unit then stalls on the L1 for about half of the moments pass.
+// Here lane i of load k takes word quad 64 k + i of the wave's range (each
+// instruction covers 1 KiB of consecutive memory, whole lines), writes it
+// to the wave's LDS rows, and reads its own segment back.  LDS rows are
+// padded to an odd number of quads (4, 12 or 20 words), which spreads the
+// per-lane 16-byte reads of eight lanes over all banks.
+typedef float f4l __attribute__((ext_vector_type(4)));   // 16-byte aligned (LDS)
+constexpr int STG_ROW = 20;                              // LDS words per row at L = 16
+
+__device__ __forceinline__ uint32_t stg_row(uint32_t L) { return L == 4 ? 4u : (L == 8 ? 12u : 20u); }
+
+// Orders this wave's LDS accesses on both sides (no instruction: a wave's
+// LDS operations complete in order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Segments of this wave in tile `tile` (0 past the end); uniform per wave.
+__device__ __forceinline__ uint32_t stage_count(const SegPlan &P, uint64_t tile)
+{
+    const uint64_t s0 = tile * NT + (threadIdx.x & ~63u);
+    if (tile >= P.ntiles || s0 >= P.nseg)
+        return 0u;
+    const uint64_t left = P.nseg - s0;
+    return left < 64u ? (uint32_t)left : 64u;
+}
+
+__device__ __forceinline__ uint32_t stage_shift(uint32_t L)   // log2(quads per row)
+{
+    return L == 4 ? 0u : (L == 8 ? 1u : 2u);
+}
+
+// The global loads of a staged tile of operand k: lane i takes quads
+// i, 64 + i, .. of the wave's range into x (indices clamped into the
+// range; the LDS pass drops the copies).
+template <bool NTL>
+__device__ __forceinline__ void stage_fetch(const SegPlan &P, int k, uint64_t tile, float x[HALF])
+{
+    const uint32_t cnt = stage_count(P, tile);
+    if (cnt == 0u)
+        return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t sh = stage_shift(P.L);
+    const uint32_t nq = cnt << sh;
+    const uint64_t s0 = tile * NT + (threadIdx.x & ~63u);
+    const GLOBAL f4v *src =
+        (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + P.base[k] +
+                             (int64_t)(s0 * P.L));
+#pragma unroll
+    for (int i = 0; i < HALF / 4; ++i) {
+        if ((uint32_t)i < (1u << sh)) {
+            const f4v y = ldg<NTL>(src + min((uint32_t)i * 64u + lane, nq - 1u));
+            x[4 * i + 0] = y.x;
+            x[4 * i + 1] = y.y;
+            x[4 * i + 2] = y.z;
+            x[4 * i + 3] = y.w;
+        }
+    }
+}
+
+// Writes the fetched quads to the wave's LDS rows and reads this lane's
+// segment back into v[0..L).  Every lane of the wave takes part.
+__device__ __forceinline__ void stage_scatter(const SegPlan &P, uint64_t tile, const float x[HALF],
+                                              SHARED float *lds, float v[HALF])
+{
+    const uint32_t cnt = stage_count(P, tile);
+    if (cnt == 0u)
+        return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t row = stg_row(P.L), sh = stage_shift(P.L);
+    const uint32_t nq = cnt << sh;
+    wave_lds_sync();   // this wave's reads of the previous tile are done
+#pragma unroll
+    for (int i = 0; i < HALF / 4; ++i) {
+        const uint32_t q = (uint32_t)i * 64u + lane;
+        if ((uint32_t)i < (1u << sh) && q < nq) {
+            const uint32_t r = q >> sh, c = q & ((1u << sh) - 1u);
+            *(SHARED f4l *)(lds + r * row + 4u * c) = f4l{x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]};
+        }
+    }
+    wave_lds_sync();
+    if (lane < cnt) {
+#pragma unroll
+        for (int i = 0; i < HALF / 4; ++i) {
+            if ((uint32_t)i < (1u << sh)) {
+                const f4l y = *(const SHARED f4l *)(lds + lane * row + 4u * (uint32_t)i);
+                v[4 * i + 0] = y.x;
+                v[4 * i + 1] = y.y;
+                v[4 * i + 2] = y.z;
+                v[4 * i + 3] = y.w;
+            }
+        }
+    }
+}
+
+template <bool NTL>
+__device__ __forceinline__ void stage_words(const SegPlan &P, int k, uint64_t tile, SHARED float *lds,
+                                            float v[HALF])
+{
+    float x[HALF];
+    stage_fetch<NTL>(P, k, tile, x);
+    stage_scatter(P, tile, x, lds, v);
+}
+
+// The weights of this lane's segment through stage_words: the float words
+// of one operand, or the float64 product over several (operand order).
+template <bool NTL, bool MULTI>
+__device__ __forceinline__ void stage_half(const SegPlan &P, uint64_t tile, SHARED float *lds,
+                                           HalfW<MULTI> &W)
+{
+    if constexpr (!MULTI) {
+        stage_words<NTL>(P, 0, tile, lds, W.w);
+    } else {
+        float v[HALF];
+        stage_words<NTL>(P, 0, tile, lds, v);
+#pragma unroll
+        for (int j = 0; j < HALF; ++j)
+            W.w[j] = (double)v[j];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            if (k < (int)P.n) {
+                stage_words<NTL>(P, k, tile, lds, v);
+#pragma unroll
+                for (int j = 0; j < HALF; ++j)
+                    W.w[j] *= (double)v[j];
+            }
+        }
+    }
+}
+
 // Element offsets of a segment's first element in every operand.
 template <int DM>
 __device__ __forceinline__ void seg_offsets(const SegPlan &P, const Seg &sg, int64_t off[4])
@@ -392,8 +540,9 @@ template <int DM, bool COV, bool MULTI> constexpr int moments_min_blocks()
 }
 
 template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true>
-__global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void moments_kernel(const SegPlan P)
+__global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void moments_kernel(const SegPlan plan)
 {
+    SEG_PLAN_FOR(DM);
     typedef Terms<DM, COV> TT;
     constexpr int T = TT::T;
     __shared__ double xch[8][NT];
@@ -710,16 +859,28 @@ __global__ __launch_bounds__(NT) void moments_adj_kernel(const SegPlan P)
 // through the same segments, loads and fixed-order reductions.
 // ---------------------------------------------------------------------
 template <int DM, bool VEC, bool MULTI, bool NTL = true>
-__global__ __launch_bounds__(NT, 4) void dot_kernel(const SegPlan P)
+__global__ __launch_bounds__(NT, 4) void dot_kernel(const SegPlan plan)
 {
+    SEG_PLAN_FOR(DM);
     __shared__ double xch[8][NT];
     __shared__ double tot[1];
+    __shared__ __align__(16) float stg[VEC ? NT / 64 : 1][VEC ? 64 * STG_ROW : 4];
     double acc[1] = {0.0};
     const uint32_t lb = seg_logical_block();
     const uint64_t g = gridDim.x;
     for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
         const uint64_t s = tile * NT + threadIdx.x;
-        if (s < P.nseg) {
+        if (VEC && P.stage) {
+            HalfW<MULTI> w0;
+            stage_half<NTL, MULTI>(P, tile, (SHARED float *)stg[threadIdx.x >> 6], w0);
+            if (s < P.nseg) {
+                const Seg sg = seg_of(P, s);
+                const int64_t off[4] = {0, 0, 0, 0};   // no second half: len <= 16
+                double s0, s1, s2;
+                seg_moments<VEC, NTL, MULTI, 0>(P, off, sg.len, w0, s0, s1, s2);
+                acc[0] += s0;
+            }
+        } else if (s < P.nseg) {
             const Seg sg = seg_of(P, s);
             int64_t off[4];
             HalfW<MULTI> w0;
@@ -828,8 +989,9 @@ __device__ __forceinline__ uint32_t seg_nonzero_half(const SegPlan &P, const int
 }
 
 template <int DM, bool VEC, bool NTL = true>
-__global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPlan P)
+__global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPlan plan)
 {
+    SEG_PLAN_FOR(DM);
     __shared__ uint32_t slo[DM], shi[DM];
     const int D = (int)P.D;
     uint32_t lo[DM], hi[DM];

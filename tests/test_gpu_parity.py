@@ -354,6 +354,55 @@ def test_moments_shapes(shape, cov):
     assert bits_equal(host(c32), host(o32)) and bits_equal(host(c64), host(o64))
 
 
+# Rows of 4, 8 or 16 words laid end to end: segment counts below one wave,
+# between waves and over several tiles, with dropped axes, one and several
+# operands and both load hints.  The inner product takes its staged tile
+# loads here (each wave loads its 64 segments line by line through LDS).
+STAGED_SHAPES = [(7, 5, 16), (33, 29, 16), (300, 8), (5, 77, 4), (2, 3, 1, 4, 3, 8), (16,),
+                 (3, 1, 257, 4), (64, 16), (65, 8, 16)]
+
+
+@pytest.mark.parametrize("shape", STAGED_SHAPES)
+@pytest.mark.parametrize("cov", [False, True])
+def test_moments_short_rows(shape, cov):
+    announce("moments short rows", shape, cov)
+    rng = inputs.rng(3, 20, len(shape), int(np.prod(shape)))
+    p = rng.gamma(0.5, 1.0, size=shape).astype(np.float32)
+    q = rng.random(shape).astype(np.float32)
+    d = len(shape)
+    want = oracle.moments(shape, [p.reshape(-1)], [shape], cov=cov)
+    for cached in (False, True):
+        o32, o64 = api.moments(dev(p), cov=cov, cached=cached)
+        _check_moments(host(o32), host(o64), want, d, cov)
+    # two operands: w = p * q per point, formed in float64
+    want2 = oracle.moments(shape, [p.reshape(-1), q.reshape(-1)], [shape, shape], cov=cov)
+    o32, o64 = api.moments(dev(p), cov=cov, others=[dev(q)])
+    _check_moments(host(o32), host(o64), want2, d, cov)
+
+
+@pytest.mark.parametrize("shape", STAGED_SHAPES)
+def test_dot_staged_rows(shape):
+    announce("dot staged", shape)
+    rng = inputs.rng(3, 21, len(shape), int(np.prod(shape)))
+    a = rng.standard_normal(shape).astype(np.float32)
+    b = rng.standard_normal(shape).astype(np.float32)
+    c = rng.standard_normal(shape).astype(np.float32)
+    n = int(np.prod(shape))
+    for ops in ([a, b], [a, b, c]):
+        want = oracle.dot(shape, ops, [shape] * len(ops))
+        mag = oracle.dot(shape, [np.abs(x) for x in ops], [shape] * len(ops))
+        o32, o64 = api.dot(*[dev(x) for x in ops])
+        g = float(host(o64)[0])
+        # float64 sums in another order: within n eps sum|w| of the oracle
+        assert abs(g - want) <= n * np.finfo(np.float64).eps * mag + 1e-300, (g, want)
+    # integer values: exact whatever the order
+    ai = rng.integers(-3, 4, size=shape).astype(np.float32)
+    bi = rng.integers(-3, 4, size=shape).astype(np.float32)
+    want = oracle.dot(shape, [ai, bi], [shape, shape])
+    o32, o64 = api.dot(dev(ai), dev(bi))
+    assert host(o64)[0] == want
+
+
 def test_moments_invariants_on_gpu():
     announce("moments invariants")
     # delta: E = t exactly
