@@ -114,7 +114,7 @@ struct SegPlan {
     uint32_t rows;            // counter rows (< 2^32)
     uint32_t full;            // every operand contiguous over the counter
     uint32_t vec4;            // every operand contiguous along the row and L % 4 == 0
-    uint32_t stage;           // DOT: full, vec4 and L in {4, 8, 16}: tiles load through LDS
+    uint32_t stage;           // DOT, BBOX: full, vec4, L in {4, 8, 16}: tiles load through LDS
     uint32_t flags;           // TRIOT_MOMENTS_* bits
     uint32_t nblocks;         // grid size (moments: number of partials)
     uint32_t nterms;          // accumulated terms: 1 + D (+ D(D+1)/2)

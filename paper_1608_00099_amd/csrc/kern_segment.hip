@@ -993,6 +993,7 @@ __global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPl
 {
     SEG_PLAN_FOR(DM);
     __shared__ uint32_t slo[DM], shi[DM];
+    __shared__ __align__(16) float stg[VEC ? NT / 64 : 1][VEC ? 64 * STG_ROW : 4];
     const int D = (int)P.D;
     uint32_t lo[DM], hi[DM];
 #pragma unroll
@@ -1008,13 +1009,34 @@ __global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPl
     const uint64_t g = gridDim.x;
     for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
         const uint64_t s = tile * NT + threadIdx.x;
+        uint32_t staged = 0xFFFFu;   // staged tiles: the nonzero mask of the segment
+        if (VEC && P.stage) {
+            SHARED float *lds = (SHARED float *)stg[threadIdx.x >> 6];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < (int)P.n) {
+                    float v[HALF];
+                    stage_words<NTL>(P, k, tile, lds, v);
+                    uint32_t mk = 0;
+#pragma unroll
+                    for (int j = 0; j < HALF; ++j)
+                        mk |= (v[j] != 0.0f ? 1u : 0u) << j;
+                    staged &= mk;
+                }
+            }
+        }
         if (s < P.nseg) {
             const Seg sg = seg_of(P, s);
             int64_t off[4];
             seg_offsets<DM>(P, sg, off);
-            uint32_t m = seg_nonzero_half<VEC, NTL>(P, off, sg.len, 0);
-            if (sg.len > (uint32_t)HALF)
-                m |= seg_nonzero_half<VEC, NTL>(P, off, sg.len, HALF) << HALF;
+            uint32_t m;
+            if (VEC && P.stage) {
+                m = staged & ((1u << sg.len) - 1u);   // len <= 16
+            } else {
+                m = seg_nonzero_half<VEC, NTL>(P, off, sg.len, 0);
+                if (sg.len > (uint32_t)HALF)
+                    m |= seg_nonzero_half<VEC, NTL>(P, off, sg.len, HALF) << HALF;
+            }
             if (m) {
                 double u[DM];
                 uint32_t tt[DM];

@@ -837,8 +837,10 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
             vec4 = false;
     P.vec4 = vec4 ? 1u : 0u;
     // Rows of 4, 8 or 16 words laid end to end: a wave's 64 segments are one
-    // contiguous range, loaded line by line through LDS (inner product).
-    P.stage = (full && vec4 && (L == 4 || L == 8 || L == 16) && r.op == TRIOT_OP_DOT) ? 1u : 0u;
+    // contiguous range, loaded line by line through LDS (inner product,
+    // bounding box).
+    P.stage = (full && vec4 && (L == 4 || L == 8 || L == 16) &&
+               (r.op == TRIOT_OP_DOT || r.op == TRIOT_OP_BBOX)) ? 1u : 0u;
     const bool cov = (flags & TRIOT_MOMENTS_COV) != 0;
     // Accumulator positions of the moments pass: exactly the kept axes with
     // the covariance (D <= 8), else a tier of 8 or 32; the adjoint keeps the

@@ -243,6 +243,31 @@ def test_bbox_matches_oracle(case, density):
     assert np.array_equal(got, want), (got, want)
 
 
+# Rows of 4, 8 or 16 words laid end to end (the staged tile loads): one and
+# two operands, sparse and denser, and single nonzeros at the first and last
+# point (a ragged last wave).
+@pytest.mark.parametrize("shape", [(7, 5, 16), (33, 29, 16), (300, 8), (5, 77, 4),
+                                   (2, 3, 1, 4, 3, 8), (65, 8, 16)])
+@pytest.mark.parametrize("density", [1e-3, 0.05])
+def test_bbox_short_rows(shape, density):
+    announce("bbox short rows", shape, density)
+    rng = inputs.rng(3, 22, len(shape), int(np.prod(shape)), int(density * 1e4))
+    a = rng.standard_normal(shape).astype(np.float32)
+    b = rng.standard_normal(shape).astype(np.float32)
+    a[rng.random(shape) >= density] = 0.0
+    b[rng.random(shape) >= 0.5] = 0.0
+    for ts in ([a], [a, b]):
+        want = oracle.bbox(shape, ts, [shape] * len(ts))
+        got = host(api.bbox(*[dev(t) for t in ts]))
+        assert np.array_equal(got, want), (ts is None, got, want)
+    for corner in (0, -1):
+        c = np.zeros(shape, np.float32)
+        c.reshape(-1)[corner] = 3.0
+        want = oracle.bbox(shape, [c], [shape])
+        got = host(api.bbox(dev(c)))
+        assert np.array_equal(got, want), (corner, got, want)
+
+
 def test_bbox_special_values_and_underflowing_products():
     announce("bbox special")
     a = np.zeros((6, 70), np.float32)
