@@ -1,6 +1,7 @@
 // Tuple-reading row kernels for gfx950: index-weighted moments (Algorithm 11
 // of the paper, read as E[t_i] of a PMF, plus the covariance of t) and their
-// adjoint (the index-weighted scatter of the gradient).
+// adjoint (the index-weighted scatter of the gradient), the inner product
+// (benchmark 2 of Section 3) and the nonzero bounding box (Section 2).
 //
 // One thread per row segment (at most SEG_MAX consecutive elements of one
 // counter row).  Inside a segment only the inner coordinate j varies, so the
@@ -13,11 +14,11 @@
 // consecutive segments, so a wave's loads cover one contiguous range.
 //
 // Partial sums are float64 per thread (on CDNA the float64 FMA issues at the
-// same rate as an unpacked float32 FMA), reduced across the wave with
-// shuffles, across the workgroup through LDS, and across workgroups by a
-// second, one-workgroup kernel that adds the per-workgroup partials in a
-// fixed tree.  No float atomics: the result is deterministic.  Ordering that
-// combine behind the first kernel by the stream, rather than by a
+// same rate as an unpacked float32 FMA), reduced across the wave by DPP,
+// across the workgroup through LDS, and across workgroups by a second
+// kernel (one wave per result) that adds the per-workgroup partials in a
+// fixed order.  No float atomics: the result is deterministic.  Ordering
+// that combine behind the first kernel by the stream, rather than by a
 // device-scope fence in every workgroup (which on CDNA writes back the whole
 // L2 of the XCD), costs one short launch.
 //
