@@ -200,6 +200,24 @@ def test_marginal_matches_oracle(case):
     assert np.all(np.abs(got32.astype(np.float64) - want) <= ulp + bound)
 
 
+# One contiguous reduced run per kept tuple, walked interleaved (lane l of a
+# chunk takes every 64th element): ragged last chunks, one and two
+# operands; integer values make every order of summation exact.
+@pytest.mark.parametrize("shape,keep", [((3, 1028), (1, 0)), ((5, 4100), (1, 0)),
+                                        ((2, 3, 16, 64), (1, 1, 0, 0)), ((3, 2051), (1, 0)),
+                                        ((1, 70000), (1, 0)), ((6, 8, 1, 2048), (1, 0, 0, 0))])
+def test_marginal_interleaved_runs(shape, keep):
+    announce("marginal interleaved", shape, keep)
+    rng = inputs.rng(3, 23, len(shape), int(np.prod(shape)))
+    a = rng.integers(0, 5, size=shape).astype(np.float32)
+    b = rng.integers(-2, 3, size=shape).astype(np.float32)
+    for ts in ([a], [a, b]):
+        want = oracle.marginal(shape, keep, ts, [shape] * len(ts))
+        o32, o64 = api.marginal(dev(ts[0]), keep, others=[dev(t) for t in ts[1:]])
+        assert np.array_equal(host(o64), want), (shape, keep, len(ts))
+        assert np.array_equal(host(o32), want.astype(np.float32))
+
+
 def test_marginal_integer_values_exact():
     announce("marginal exact")
     rng = np.random.default_rng(270)
