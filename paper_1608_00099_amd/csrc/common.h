@@ -17,6 +17,7 @@ constexpr uint32_t NOBOUND = 0xFFFFFFFFu;
 constexpr int NT = 256;           // threads per workgroup (4 wave64)
 constexpr int RB_MAX = 1024;      // LDS row-table capacity (rows per box)
 constexpr int SEG_MAX = 32;       // per-thread segment length of the row kernels
+constexpr int DOT_QUADS = 4;      // word quads per lane and tile of the inner product's quad walk
 constexpr int MOM_TERMS_MAX = 1 + MAXD + 8 * 9 / 2;  // covariance limited to 8 axes
 
 // Internal op ids of the element-wise family (kernel template argument).
@@ -115,6 +116,9 @@ struct SegPlan {
     uint32_t full;            // every operand contiguous over the counter
     uint32_t vec4;            // every operand contiguous along the row and L % 4 == 0
     uint32_t stage;           // DOT, BBOX: full, vec4, L in {4, 8, 16}: tiles load through LDS
+    uint32_t quads;           // DOT: one word quad per lane (vec4, quads < 2^31, not staged)
+    AxisDiv qdiv;             // quads: quad -> (row, quad in row), divisor L / 4
+    uint64_t nquads;          // quads: rows * L / 4
     uint32_t flags;           // TRIOT_MOMENTS_* bits
     uint32_t nblocks;         // grid size (moments: number of partials)
     uint32_t nterms;          // accumulated terms: 1 + D (+ D(D+1)/2)

@@ -869,27 +869,78 @@ __global__ __launch_bounds__(NT, 4) void dot_kernel(const SegPlan plan)
     double acc[1] = {0.0};
     const uint32_t lb = seg_logical_block();
     const uint64_t g = gridDim.x;
-    for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
-        const uint64_t s = tile * NT + threadIdx.x;
-        if (VEC && P.stage) {
-            HalfW<MULTI> w0;
-            stage_half<NTL, MULTI>(P, tile, (SHARED float *)stg[threadIdx.x >> 6], w0);
-            if (s < P.nseg) {
+    if (VEC && P.quads) {
+        // One word quad per lane: tile t holds quads t * NT * DOT_QUADS + u * NT
+        // + i (u < DOT_QUADS), so each load instruction of the workgroup
+        // covers NT consecutive quads (whole rows of the counter).
+        const int D = (int)P.D;
+        const uint32_t qpr = P.qdiv.c;
+        for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
+            const uint32_t q0 = (uint32_t)(tile * NT * DOT_QUADS) + threadIdx.x;
+            f4v x[DOT_QUADS][4];
+            bool ok[DOT_QUADS];
+#pragma unroll
+            for (int u = 0; u < DOT_QUADS; ++u) {
+                const uint32_t q = q0 + (uint32_t)(u * NT);
+                ok[u] = q < P.nquads;
+                const uint32_t qq = ok[u] ? q : 0u;
+                const uint32_t row = qpr == 1u ? qq : sdiv_u32(qq, P.qdiv);
+                const uint32_t col = qq - row * qpr;
+                double uu[DM];
+                uint32_t tt[DM];
+                row_coords<DM>(P, row, uu, tt);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (k < (int)P.n) {
+                        const int64_t off = row_offset<DM>(P, k, tt) + (int64_t)col * 4 * P.stride[k][D - 1];
+                        x[u][k] = ldg<NTL>((const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + off));
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < DOT_QUADS; ++u) {
+                if (ok[u]) {
+                    double w[4] = {(double)x[u][0].x, (double)x[u][0].y, (double)x[u][0].z,
+                                   (double)x[u][0].w};
+#pragma unroll
+                    for (int k = 1; k < 4; ++k) {
+                        if (k < (int)P.n) {
+                            w[0] *= (double)x[u][k].x;
+                            w[1] *= (double)x[u][k].y;
+                            w[2] *= (double)x[u][k].z;
+                            w[3] *= (double)x[u][k].w;
+                        }
+                    }
+                    acc[0] += w[0];
+                    acc[0] += w[1];
+                    acc[0] += w[2];
+                    acc[0] += w[3];
+                }
+            }
+        }
+    } else {
+        for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
+            const uint64_t s = tile * NT + threadIdx.x;
+            if (VEC && P.stage) {
+                HalfW<MULTI> w0;
+                stage_half<NTL, MULTI>(P, tile, (SHARED float *)stg[threadIdx.x >> 6], w0);
+                if (s < P.nseg) {
+                    const Seg sg = seg_of(P, s);
+                    const int64_t off[4] = {0, 0, 0, 0};   // no second half: len <= 16
+                    double s0, s1, s2;
+                    seg_moments<VEC, NTL, MULTI, 0>(P, off, sg.len, w0, s0, s1, s2);
+                    acc[0] += s0;
+                }
+            } else if (s < P.nseg) {
                 const Seg sg = seg_of(P, s);
-                const int64_t off[4] = {0, 0, 0, 0};   // no second half: len <= 16
+                int64_t off[4];
+                HalfW<MULTI> w0;
+                seg_offsets<DM>(P, sg, off);
+                seg_load_half<VEC, NTL, MULTI>(P, off, sg.len, 0, w0);
                 double s0, s1, s2;
                 seg_moments<VEC, NTL, MULTI, 0>(P, off, sg.len, w0, s0, s1, s2);
                 acc[0] += s0;
             }
-        } else if (s < P.nseg) {
-            const Seg sg = seg_of(P, s);
-            int64_t off[4];
-            HalfW<MULTI> w0;
-            seg_offsets<DM>(P, sg, off);
-            seg_load_half<VEC, NTL, MULTI>(P, off, sg.len, 0, w0);
-            double s0, s1, s2;
-            seg_moments<VEC, NTL, MULTI, 0>(P, off, sg.len, w0, s0, s1, s2);
-            acc[0] += s0;
         }
     }
     block_sums<1>(acc, xch, tot);

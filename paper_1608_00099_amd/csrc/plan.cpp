@@ -841,6 +841,17 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     // bounding box).
     P.stage = (full && vec4 && (L == 4 || L == 8 || L == 16) &&
                (r.op == TRIOT_OP_DOT || r.op == TRIOT_OP_BBOX)) ? 1u : 0u;
+    // Inner product over other layouts of whole quads: one quad per lane, so
+    // that the 8 lanes of a 32-word row load its 128 bytes together (with a
+    // segment per lane, every load instruction touches 64 lines).
+    const uint64_t nquads = (uint64_t)rows * (uint64_t)(L / 4);
+    P.quads = (vec4 && !P.stage && r.op == TRIOT_OP_DOT && nquads < (uint64_t(1) << 31)) ? 1u : 0u;
+    if (P.quads) {
+        P.nquads = nquads;
+        if (!magic_for((uint32_t)(L / 4), &P.qdiv))
+            P.qdiv = trivial_div();            // one quad per row: row = quad
+        P.ntiles = (nquads + (uint64_t)NT * DOT_QUADS - 1) / ((uint64_t)NT * DOT_QUADS);
+    }
     const bool cov = (flags & TRIOT_MOMENTS_COV) != 0;
     // Accumulator positions of the moments pass: exactly the kept axes with
     // the covariance (D <= 8), else a tier of 8 or 32; the adjoint keeps the

@@ -403,6 +403,36 @@ def test_dot_staged_rows(shape):
     assert host(o64)[0] == want
 
 
+# Windows whose rows are whole word quads (the inner product's quad walk:
+# one quad per lane): inner extents 4 .. 100, ragged last tiles, two and
+# three operands, and a single long row.
+QUAD_CASES = [((37, 41, 32), (40, 39, 36)), ((9, 10, 8), (12, 9, 8)), ((50, 12), (51, 13)),
+              ((3, 7, 5, 64), (4, 7, 6, 66)), ((300, 100), (301, 104)), ((70000,), (65540,)),
+              ((2, 1, 33, 4), (3, 1, 34, 4))]
+
+
+@pytest.mark.parametrize("case", range(len(QUAD_CASES)))
+def test_dot_quad_walk(case):
+    sa, sb = QUAD_CASES[case]
+    announce("dot quads", sa, sb)
+    rng = inputs.rng(3, 24, case)
+    a = rng.standard_normal(sa).astype(np.float32)
+    b = rng.standard_normal(sb).astype(np.float32)
+    counter = tuple(min(x, y) for x, y in zip(sa, sb))
+    n = int(np.prod(counter))
+    for ops, shapes in (([a, b], [sa, sb]), ([a, b, b], [sa, sb, sb])):
+        want = oracle.dot(counter, ops, shapes)
+        mag = oracle.dot(counter, [np.abs(x) for x in ops], shapes)
+        o32, o64 = api.dot(*[dev(x) for x in ops])
+        g = float(host(o64)[0])
+        assert abs(g - want) <= n * np.finfo(np.float64).eps * mag + 1e-300, (g, want)
+    ai = rng.integers(-3, 4, size=sa).astype(np.float32)
+    bi = rng.integers(-3, 4, size=sb).astype(np.float32)
+    want = oracle.dot(counter, [ai, bi], [sa, sb])
+    o32, o64 = api.dot(dev(ai), dev(bi))
+    assert host(o64)[0] == want
+
+
 def test_moments_invariants_on_gpu():
     announce("moments invariants")
     # delta: E = t exactly
