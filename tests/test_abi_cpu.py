@@ -2,6 +2,7 @@
 exports every symbol include/triot.h declares, validation returns the
 documented codes, the magic-division constants are exact, and the planner
 drops and merges axes as described."""
+import json
 import os
 import re
 
@@ -273,3 +274,50 @@ def test_batched_overlap_check_many_items():
     assert _batched_status(L.OP_COPY, items) in {L.E_DEVICE, L.OK}
     items[300] = (1, 2, sh, None, [P0 + 32 * 300 - 4, P1], None)
     assert _batched_status(L.OP_COPY, items) == L.E_ALIAS
+
+
+def test_tune_cache_file_skips_corrupt_lines(tmp_path):
+    """TRIOT_TUNE_CACHE: well-formed entries are loaded; garbage, truncated
+    lines and entries with out-of-range knobs are ignored (defaults stay).
+    In a fresh process, since the file is read once per process."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.jsonl"
+    script = tmp_path / "probe.py"
+    script.write_text(r'''
+import json, os, sys
+sys.path.insert(0, %r)
+from paper_1608_00099_amd import _lib as L
+
+def key(shape):
+    s = ":s%%d,%%d,b0,a0" %% shape
+    return "op%%d:n3:e4:d2:c%%d,%%d," %% ((L.OP_MUL_ACC,) + shape) + s * 3
+
+def get(shape):
+    ptrs = [(k + 1) << 40 for k in range(3)]
+    st, s = L.triot_schedule_get(L.OP_MUL_ACC, 3, 2, [shape] * 3, None, ptrs, None, None)
+    assert st == L.OK
+    return [s.vec_max, s.cache_policy, s.blocks_per_cu, s.box_rows_max, s.unit_elems, s.unit_order]
+
+if sys.argv[1] == "keys":
+    print(json.dumps([key((8, 40)), key((9, 40)), key((10, 40))]))
+else:
+    print(json.dumps([get((8, 40)), get((9, 40)), get((10, 40))]))
+''' % ROOT)
+    env = dict(os.environ)
+    env.pop("TRIOT_TUNE_CACHE", None)
+    keys = json.loads(subprocess.run([sys.executable, str(script), "keys"], env=env, check=True,
+                                     capture_output=True, text=True).stdout)
+    cache.write_text("\n".join([
+        "not a cache line",
+        '{"key": "%s", "vec": 2, "cache": 0, "bpc": 8, "order": 1, "rb": 64, "pe": 2048}' % keys[0],
+        '{"key": "%s", "vec": 3, "cache": 0, "bpc": 8, "order": 1, "rb": 64, "pe": 2048}' % keys[1],
+        '{"key": "%s", "vec": 4, "cache": 1' % keys[2],
+        "",
+    ]) + "\n")
+    env["TRIOT_TUNE_CACHE"] = str(cache)
+    got = json.loads(subprocess.run([sys.executable, str(script), "get"], env=env, check=True,
+                                    capture_output=True, text=True).stdout)
+    default = [4, 1, 4, 1024, 8192, 0]
+    assert got[0] == [2, 0, 8, 64, 2048, 1]
+    assert got[1] == default and got[2] == default
