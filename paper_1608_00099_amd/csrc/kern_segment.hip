@@ -260,10 +260,18 @@ template <bool NTL> __device__ __forceinline__ float ldg(const GLOBAL float *p)
 template <bool MULTI> struct HalfW {
     float w[HALF];
     __device__ __forceinline__ double at(int j) const { return (double)w[j]; }
+    __device__ __forceinline__ double at_or_zero(int j, bool keep) const
+    {
+        return (double)(keep ? w[j] : 0.0f);
+    }
 };
 template <> struct HalfW<true> {
     double w[HALF];
     __device__ __forceinline__ double at(int j) const { return w[j]; }
+    __device__ __forceinline__ double at_or_zero(int j, bool keep) const
+    {
+        return keep ? w[j] : 0.0;
+    }
 };
 
 // Loads words [h0, h0 + HALF) of a segment of every operand.  VEC: 16-byte
@@ -363,6 +371,45 @@ __device__ __forceinline__ void seg_moments(const SegPlan &P, const int64_t off[
     } else {
         s2 = 0.0;
     }
+}
+
+// The same three sums for the moments pass, formed directly: the
+// multipliers j and j^2 are compile-time constants of the unrolled loop, so
+// each element costs one float64 addition and two fused multiply-adds, in
+// two independent partial sums per moment (no running-sum chain).
+// Elements past len (the loads are clamped into the segment) enter as
+// zero, a select on the loaded word; when every segment is HALF words long
+// (S == HALF, G == 1: uniform over the launch) no select is needed.  Fewer
+// registers than the running sums (the covariance instance of 6 axes: 126
+// VGPRs against 138), which lets the staged pass run 3 workgroups per CU.
+template <bool VEC, bool NTL, bool MULTI>
+__device__ __forceinline__ void seg_sums_fma(const SegPlan &P, const int64_t off[4], uint32_t len,
+                                             const HalfW<MULTI> &w0, double &s0, double &s1,
+                                             double &s2)
+{
+    double a[2] = {0.0, 0.0}, b[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+    const bool whole = P.S == (uint32_t)HALF && P.G == 1u;   // len == HALF everywhere
+    HalfW<MULTI> w1;
+    if (!whole && len > (uint32_t)HALF)
+        seg_load_half<VEC, NTL, MULTI>(P, off, len, HALF, w1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t h0 = (uint32_t)(h * HALF);
+        if (h == 0 || (!whole && len > h0)) {
+            const HalfW<MULTI> &W = (h == 0) ? w0 : w1;
+#pragma unroll
+            for (int j = 0; j < HALF; ++j) {
+                const double w = whole ? W.at(j) : W.at_or_zero(j, h0 + (uint32_t)j < len);
+                const int jj = h * HALF + j;
+                a[j & 1] += w;
+                b[j & 1] = fma((double)jj, w, b[j & 1]);
+                c[j & 1] = fma((double)(jj * jj), w, c[j & 1]);
+            }
+        }
+    }
+    s0 = a[0] + a[1];
+    s1 = b[0] + b[1];
+    s2 = c[0] + c[1];
 }
 
 // Staged tile loads (plan flag `stage`: every operand contiguous over the
@@ -540,7 +587,7 @@ template <int DM, bool COV, bool MULTI> constexpr int moments_min_blocks()
     return 2;
 }
 
-template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true>
+template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true, bool STG = false>
 __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void moments_kernel(const SegPlan plan)
 {
     SEG_PLAN_FOR(DM);
@@ -548,6 +595,7 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
     constexpr int T = TT::T;
     __shared__ double xch[8][NT];
     __shared__ double tot[T];
+    __shared__ __align__(16) float stg[STG ? NT / 64 : 1][STG ? 64 * STG_ROW : 4];
 
     double acc[T];
 #pragma unroll
@@ -565,7 +613,13 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
         Seg sg{0, 0, 0};
         int64_t off[4];
         HalfW<MULTI> w0;
-        if (valid) {
+        if constexpr (STG) {
+            stage_half<NTL, MULTI>(P, tile, (SHARED float *)stg[threadIdx.x >> 6], w0);
+            if (valid) {
+                sg = seg_of(P, s);
+                seg_offsets<DM>(P, sg, off);
+            }
+        } else if (valid) {
             sg = seg_of(P, s);
             seg_offsets<DM>(P, sg, off);
             seg_load_half<VEC, NTL, MULTI>(P, off, sg.len, 0, w0);
@@ -575,7 +629,7 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
             uint32_t tt[DM];
             row_coords<DM>(P, sg.row, u, tt);
             double s0, s1, s2;
-            seg_moments<VEC, NTL, MULTI, COV ? 2 : 1>(P, off, sg.len, w0, s0, s1, s2);
+            seg_sums_fma<VEC, NTL, MULTI>(P, off, sg.len, w0, s0, s1, s2);
             // inner axis: u_in = a + j with a = j0 - centre
             const double a = (double)sg.j0 - cin;
             const double A1 = fma(a, s0, s1);                       // sum w u_in
@@ -1223,6 +1277,15 @@ static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
     const bool multi = L.plan.n > 1;
     const bool cached = (L.plan.flags & TRIOT_MOMENTS_CACHED) != 0;
     const int k = (L.plan.vec4 ? 4 : 0) + (multi ? 2 : 0) + (cached ? 1 : 0);
+    if (L.plan.stage) {   // staged tile loads: an instance of their own (its LDS rows)
+        switch (k) {
+        case 7: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, false, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 6: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 5: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        default: return hipErrorInvalidValue;   // the plan stages whole-quad rows only
+        }
+    } else {
     switch (k) {
     case 7: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
     case 6: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
@@ -1232,6 +1295,7 @@ static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
     case 2: hipLaunchKernelGGL((moments_kernel<DM, COV, false, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
     case 1: hipLaunchKernelGGL((moments_kernel<DM, COV, false, false, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
     default: hipLaunchKernelGGL((moments_kernel<DM, COV, false, false, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+    }
     }
     const int d = (int)L.plan.d_orig;
     const int nout = 1 + d + (COV ? d * (d + 1) / 2 : 0);
@@ -1331,17 +1395,18 @@ template <class K> static int occupancy(K kernel)
     return (e == hipSuccess && nb > 0) ? nb : 2;
 }
 
-template <int DM, bool COV> static int occ_moments(bool vec4)
+template <int DM, bool COV> static int occ_moments(bool vec4, bool stage)
 {
-    static int cache[2] = {0, 0};
-    int &c = cache[vec4 ? 1 : 0];
+    static int cache[3] = {0, 0, 0};
+    int &c = cache[stage ? 2 : (vec4 ? 1 : 0)];
     if (!c)
-        c = vec4 ? occupancy(moments_kernel<DM, COV, true, false>)
-                 : occupancy(moments_kernel<DM, COV, false, false>);
+        c = stage  ? occupancy(moments_kernel<DM, COV, true, false, true, true>)
+            : vec4 ? occupancy(moments_kernel<DM, COV, true, false>)
+                   : occupancy(moments_kernel<DM, COV, false, false>);
     return c;
 }
 
-int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4)
+int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4, bool stage)
 {
     if (adj) {
         static int cache[3] = {0, 0, 0};
@@ -1354,17 +1419,17 @@ int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4)
     }
     if (cov) {
         switch (dm) {
-        case 1: return occ_moments<1, true>(vec4);
-        case 2: return occ_moments<2, true>(vec4);
-        case 3: return occ_moments<3, true>(vec4);
-        case 4: return occ_moments<4, true>(vec4);
-        case 5: return occ_moments<5, true>(vec4);
-        case 6: return occ_moments<6, true>(vec4);
-        case 7: return occ_moments<7, true>(vec4);
-        default: return occ_moments<8, true>(vec4);
+        case 1: return occ_moments<1, true>(vec4, stage);
+        case 2: return occ_moments<2, true>(vec4, stage);
+        case 3: return occ_moments<3, true>(vec4, stage);
+        case 4: return occ_moments<4, true>(vec4, stage);
+        case 5: return occ_moments<5, true>(vec4, stage);
+        case 6: return occ_moments<6, true>(vec4, stage);
+        case 7: return occ_moments<7, true>(vec4, stage);
+        default: return occ_moments<8, true>(vec4, stage);
         }
     }
-    return dm <= 8 ? occ_moments<8, false>(vec4) : occ_moments<32, false>(vec4);
+    return dm <= 8 ? occ_moments<8, false>(vec4, stage) : occ_moments<32, false>(vec4, stage);
 }
 
 }  // namespace triot

@@ -838,9 +838,12 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     P.vec4 = vec4 ? 1u : 0u;
     // Rows of 4, 8 or 16 words laid end to end: a wave's 64 segments are one
     // contiguous range, loaded line by line through LDS (inner product,
-    // bounding box).
-    P.stage = (full && vec4 && (L == 4 || L == 8 || L == 16) &&
-               (r.op == TRIOT_OP_DOT || r.op == TRIOT_OP_BBOX)) ? 1u : 0u;
+    // bounding box; the moments pass for rows of 16 words from 2^21 rows
+    // on, measured faster there and slower below).
+    const bool stage_rows = full && vec4 && (L == 4 || L == 8 || L == 16);
+    const bool stage_moments = r.op == TRIOT_OP_MOMENTS && L == 16 && rows >= (int64_t(1) << 21);
+    P.stage = (stage_rows && (r.op == TRIOT_OP_DOT || r.op == TRIOT_OP_BBOX || stage_moments))
+                  ? 1u : 0u;
     // Inner product over other layouts of whole quads: one quad per lane, so
     // that the 8 lanes of a 32-word row load its 128 bytes together (with a
     // segment per lane, every load instruction touches 64 lines).
@@ -868,14 +871,16 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
         P.nterms = (uint32_t)(2 * dm);      // lo and hi + 1 per position (32-bit words)
 
     // Persistent grid: as many workgroups as can be resident at once (for
-    // the moments pass at most 2 per CU: each workgroup ends in a reduction
-    // of every term, and measured on MI355X, 2 per CU beat 4).
+    // the moments pass at most 2 per CU, 3 when staged: each workgroup ends
+    // in a reduction of every term, and measured on MI355X, 2 per CU beat 3
+    // and 4 on the per-lane loads).
     const bool adj = r.op == TRIOT_OP_MOMENTS_ADJ;
     int bpc = 2;   // the inner product and the bounding box: 2 per CU
     if (r.op == TRIOT_OP_MOMENTS || adj)
-        bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4);
+        bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4, P.stage != 0);
+    // (the staged moments pass: 3 per CU, measured faster on large inputs)
     if (!adj)
-        bpc = std::min(bpc, 2);
+        bpc = std::min(bpc, (r.op == TRIOT_OP_MOMENTS && P.stage) ? 3 : 2);
     int64_t blocks = std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * bpc);
     if (blocks > 8)
         blocks = (blocks + 7) / 8 * 8;

@@ -380,6 +380,26 @@ def test_moments_short_rows(shape, cov):
     _check_moments(host(o32), host(o64), want2, d, cov)
 
 
+# Rows of 16 words laid end to end from 2^21 rows on: the moments pass
+# takes the staged tile loads, 3 workgroups per CU (just below: per-lane
+# loads); one and two operands.
+@pytest.mark.parametrize("shape", [(2048, 1024, 16), (2047, 1024, 16), (8192, 257, 16)])
+def test_moments_large_staged(shape):
+    announce("moments large staged", shape)
+    rng = inputs.rng(3, 25, shape[0], shape[1])
+    p = rng.random(shape, dtype=np.float32)
+    d = len(shape)
+    for cov in (True, False):
+        want = oracle.moments(shape, [p.reshape(-1)], [shape], cov=cov)
+        o32, o64 = api.moments(dev(p), cov=cov)
+        _check_moments(host(o32), host(o64), want, d, cov)
+    if shape[0] == 2048:
+        q = rng.random(shape, dtype=np.float32)
+        want = oracle.moments(shape, [p.reshape(-1), q.reshape(-1)], [shape, shape], cov=True)
+        o32, o64 = api.moments(dev(p), cov=True, others=[dev(q)])
+        _check_moments(host(o32), host(o64), want, d, True)
+
+
 @pytest.mark.parametrize("shape", STAGED_SHAPES)
 def test_dot_staged_rows(shape):
     announce("dot staged", shape)
