@@ -160,7 +160,11 @@ struct MargPlan {
     // multiple of 4, part boundaries multiples of 4); mode 2 interleaved
     // (one reduced axis, contiguous in every operand: lane l of a wave
     // takes elements chunk * clen + l + 64 s, so a wave's loads are
-    // coalesced).
+    // coalesced); mode 4 columns (one kept axis, innermost and unit-stride,
+    // one reduced axis: thread (q, p) adds outputs 4q .. 4q + 3 over rows
+    // p, p + parts, .., so a wave's loads cover consecutive rows); mode 5
+    // short runs (one reduced axis, innermost and unit-stride, of 4 .. 64
+    // elements, a power of 2: nred / 4 lanes per output, a word quad each).
     uint32_t mode;
     uint32_t clen;            // mode 2: elements per chunk (64 lanes)
     uint64_t nout;            // kept tuples (< 2^32)

@@ -556,26 +556,136 @@ __global__ __launch_bounds__(MARG_NT) void marginal_inter_kernel(const MargPlan 
     ((double *)((char *)(uintptr_t)P.ws + 256))[(uint64_t)o * P.parts + p] = acc;
 }
 
-// One workgroup per output: thread t adds parts t, t + MARG_NT, .. (16
-// loads in flight per thread), then the workgroup folds in a fixed tree
-// (wave butterflies, then the waves' sums in order).
-__global__ __launch_bounds__(MARG_NT) void marginal_final_kernel(const MargPlan P)
+// Columns: one kept axis, innermost and unit-stride in every operand, and
+// one reduced axis.  Thread (q, p), q fastest, adds outputs 4q .. 4q + 3
+// (one 16-byte load per operand and row) over rows p, p + parts, p +
+// 2 parts, .. in order, so the lanes of a wave read consecutive rows: a
+// contiguous range when the rows are adjacent.  The parts are combined in
+// order by the final kernels.
+__global__ __launch_bounds__(MARG_NT) void marginal_cols_kernel(const MargPlan P)
 {
-    __shared__ double ws[MARG_NT / 64];
+    const uint32_t quads = (uint32_t)(P.nout / 4);
+    const uint64_t gid = (uint64_t)blockIdx.x * MARG_NT + threadIdx.x;
+    if (gid >= (uint64_t)quads * P.parts)
+        return;
+    const uint32_t q = (uint32_t)(gid % quads);
+    const uint64_t p = gid / quads;
+    const int n = (int)P.n;
+    constexpr int LA = 8;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint64_t r0 = p; r0 < P.nred; r0 += (uint64_t)LA * P.parts) {
+        float v[LA][4][4];
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            const uint64_t r = r0 + (uint64_t)u * P.parts;
+            const uint64_t rr = r < P.nred ? r : p;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < n) {
+                    const mf4 x = *(const GLOBAL mf4 *)((const GLOBAL float *)(uintptr_t)P.ptr[k] +
+                                                       P.base[k] + 4 * (int64_t)q +
+                                                       (int64_t)rr * P.rstride[k][0]);
+                    v[u][k][0] = x.x;
+                    v[u][k][1] = x.y;
+                    v[u][k][2] = x.z;
+                    v[u][k][3] = x.w;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            if (r0 + (uint64_t)u * P.parts < P.nred) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    double w = 1.0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (k < n)
+                            w *= (double)v[u][k][e];
+                    acc[e] += w;
+                }
+            }
+        }
+    }
+    double *part = (double *)((char *)(uintptr_t)P.ws + 256);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        part[(uint64_t)(4 * q + (uint32_t)e) * P.parts + p] = acc[e];
+}
+
+// Short runs: the one reduced axis is innermost and unit-stride, of R = 4
+// .. 64 elements (a power of 2).  Lane group g = R / 4 per output: lane c of
+// the group loads quad c of the run (so a wave's loads cover 64 consecutive
+// quads when the runs are adjacent), adds its four weights in order, and
+// the group folds its sums by butterflies (fixed order); lane 0 of the
+// group writes the output.  Lanes past the last output load output 0's run
+// and write nothing (every lane takes part in the butterflies).  (Four
+// blocks of quads per workgroup, their loads in flight together, measured
+// no faster.)
+__global__ __launch_bounds__(MARG_NT) void marginal_runs_kernel(const MargPlan P)
+{
+    const uint32_t g = (uint32_t)(P.nred / 4);
+    const uint64_t gid = (uint64_t)blockIdx.x * MARG_NT + threadIdx.x;
+    const uint64_t o = gid / g;
+    const uint32_t c = (uint32_t)(gid % g);
+    const bool ok = o < P.nout;
+    const int n = (int)P.n;
+    int64_t off[4];
+    marginal_kept(P, ok ? (uint32_t)o : 0u, off);
+    float v[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < n) {
+            const mf4 x = *(const GLOBAL mf4 *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k] +
+                                               4 * (int64_t)c);
+            v[k][0] = x.x;
+            v[k][1] = x.y;
+            v[k][2] = x.z;
+            v[k][3] = x.w;
+        }
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        double w = 1.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < n)
+                w *= (double)v[k][e];
+        acc += w;
+    }
+    for (uint32_t k = 1; k < g; k <<= 1)
+        acc += __shfl_xor(acc, (int)k, 64);
+    if (ok && c == 0) {
+        ((float *)(uintptr_t)P.out32)[o] = (float)acc;
+        if (P.out64)
+            ((double *)(uintptr_t)P.out64)[o] = acc;
+    }
+}
+
+// One workgroup of MARG_FNT threads per output: thread t adds parts t,
+// t + MARG_FNT, .. (16 loads in flight per thread: up to 16384 parts in one
+// round trip), then the workgroup folds in a fixed tree (wave butterflies,
+// then the waves' sums in order).
+constexpr int MARG_FNT = 1024;
+
+__global__ __launch_bounds__(MARG_FNT) void marginal_final_kernel(const MargPlan P)
+{
+    __shared__ double ws[MARG_FNT / 64];
     const uint64_t o = blockIdx.x;
     const GLOBAL double *part = (const GLOBAL double *)((uintptr_t)P.ws + 256) + o * P.parts;
     constexpr int K = 16;
     double acc = 0.0;
-    for (uint32_t b = threadIdx.x; b < P.parts; b += K * MARG_NT) {
+    for (uint32_t b = threadIdx.x; b < P.parts; b += K * MARG_FNT) {
         double x[K];
 #pragma unroll
         for (int u = 0; u < K; ++u) {
-            const uint32_t p = b + (uint32_t)u * MARG_NT;
+            const uint32_t p = b + (uint32_t)u * MARG_FNT;
             x[u] = part[p < P.parts ? p : 0u];
         }
 #pragma unroll
         for (int u = 0; u < K; ++u)
-            if (b + (uint32_t)u * MARG_NT < P.parts)
+            if (b + (uint32_t)u * MARG_FNT < P.parts)
                 acc += x[u];
     }
 #pragma unroll
@@ -586,7 +696,7 @@ __global__ __launch_bounds__(MARG_NT) void marginal_final_kernel(const MargPlan 
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < MARG_NT / 64; ++w)
+        for (int w = 0; w < MARG_FNT / 64; ++w)
             t += ws[w];
         ((float *)(uintptr_t)P.out32)[o] = (float)t;
         if (P.out64)
@@ -634,16 +744,22 @@ template <int W> static void go_marginal(const MargLaunch &L, uint32_t blocks, h
 
 hipError_t launch_marginal(const MargLaunch &L, hipStream_t st)
 {
-    const uint64_t total = L.plan.nout * L.plan.parts;
+    const uint64_t total = L.plan.mode == 5   ? L.plan.nout * (L.plan.nred / 4)
+                           : L.plan.mode == 4 ? L.plan.nout / 4 * L.plan.parts
+                                              : L.plan.nout * L.plan.parts;
     const uint32_t blocks = (uint32_t)((total + MARG_NT - 1) / MARG_NT);
-    if (L.plan.mode == 2)
+    if (L.plan.mode == 5)
+        hipLaunchKernelGGL(marginal_runs_kernel, dim3(blocks), dim3(MARG_NT), 0, st, L.plan);
+    else if (L.plan.mode == 4)
+        hipLaunchKernelGGL(marginal_cols_kernel, dim3(blocks), dim3(MARG_NT), 0, st, L.plan);
+    else if (L.plan.mode == 2)
         hipLaunchKernelGGL(marginal_inter_kernel, dim3(blocks), dim3(MARG_NT), 0, st, L.plan);
     else if (L.plan.mode == 1)
         go_marginal<4>(L, blocks, st);
     else
         go_marginal<1>(L, blocks, st);
     if (L.plan.parts >= 256) {
-        hipLaunchKernelGGL(marginal_final_kernel, dim3((uint32_t)L.plan.nout), dim3(MARG_NT), 0, st,
+        hipLaunchKernelGGL(marginal_final_kernel, dim3((uint32_t)L.plan.nout), dim3(MARG_FNT), 0, st,
                            L.plan);
     } else if (L.plan.parts > 1) {
         const uint32_t fb = (uint32_t)((L.plan.nout + MARG_NT - 1) / MARG_NT);

@@ -978,6 +978,15 @@ size_t marginal_workspace_bytes(int cus)
     return 256 + (size_t)(2 * marginal_thread_target(cus)) * sizeof(double);
 }
 
+// Every operand's kept axis (the only one) has unit stride.
+static bool kept_unit(const MargPlan &P, int n)
+{
+    for (int k = 0; k < n; ++k)
+        if (P.kstride[k][0] != 1)
+            return false;
+    return true;
+}
+
 triot_status plan_marginal(const Request &r, int cus, MargLaunch *out)
 {
     std::memset(out, 0, sizeof(*out));
@@ -1051,7 +1060,12 @@ triot_status plan_marginal(const Request &r, int cus, MargLaunch *out)
     const int64_t target = marginal_thread_target(cus);
     uint64_t parts = 1;
     uint32_t mode = 0, clen = 0;
-    if (inner_unit && dr == 1 && nred >= 1024 && (int64_t)nout * 64 <= target) {
+    if (inner_unit && dr == 1 && (nred == 4 || nred == 8 || nred == 16 || nred == 32 ||
+                                  nred == 64) && (int64_t)nout * 64 > target) {
+        // short runs: nred / 4 lanes per output, one word quad each, summed
+        // by butterflies inside the lane group
+        mode = 5;
+    } else if (inner_unit && dr == 1 && nred >= 1024 && (int64_t)nout * 64 <= target) {
         // interleaved: chunks of >= 1024 elements, 64 lanes each
         const uint64_t chunks = std::max<uint64_t>(
             1, std::min<uint64_t>((nred + 1023) / 1024, (uint64_t)(target / ((int64_t)nout * 64))));
@@ -1059,6 +1073,14 @@ triot_status plan_marginal(const Request &r, int cus, MargLaunch *out)
         clen = (clen + 63) / 64 * 64;
         parts = 64 * ((nred + clen - 1) / clen);
         mode = 2;
+    } else if (dk == 1 && dr == 1 && ax[na - 1].keep && nout % 4 == 0 && nout <= 1024 &&
+               (int64_t)nout < target && nred >= 256 && kept_unit(P, n)) {
+        // columns: the kept axis is innermost and unit-stride, one reduced
+        // axis; a lane takes four consecutive outputs, rows p, p + parts, ..
+        // (nout * parts partials: at most 2 * target, the workspace's size)
+        parts = std::min<uint64_t>((uint64_t)(2 * target) / nout, nred / 64);
+        parts = std::max<uint64_t>(parts, 1);
+        mode = 4;
     } else {
         const bool vec = inner_unit && (P.rax[dr - 1].c % 4) == 0;
         const uint64_t units = vec ? nred / 4 : nred;   // parts split whole vectors

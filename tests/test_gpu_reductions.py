@@ -218,6 +218,65 @@ def test_marginal_interleaved_runs(shape, keep):
         assert np.array_equal(host(o32), want.astype(np.float32))
 
 
+# A kept innermost axis (the column walk: four outputs per lane, rows
+# interleaved over the parts) and its near misses: output counts not a
+# multiple of 4, a kept axis that is not unit-stride in every operand,
+# two operands, rows not a multiple of the parts.
+@pytest.mark.parametrize("shapes,keep", [
+    ([(16, 16, 16, 16, 16, 16)], (0, 0, 0, 0, 0, 1)),
+    ([(300, 64)], (0, 1)),
+    ([(7, 40, 12)], (0, 0, 1)),
+    ([(7, 40, 12), (7, 40, 12)], (0, 0, 1)),
+    ([(1001, 8)], (0, 1)),
+    ([(513, 10)], (0, 1)),
+    ([(40, 30, 20), (41, 30, 22)], (0, 0, 1)),
+])
+def test_marginal_kept_inner(shapes, keep):
+    announce("marginal kept inner", shapes, keep)
+    rng = inputs.rng(3, 26, len(shapes), len(shapes[0]), int(np.prod(shapes[0])))
+    ts = [rng.integers(0, 5, size=s).astype(np.float32) for s in shapes]
+    counter = tuple(min(s[i] for s in shapes) for i in range(len(shapes[0])))
+    want = oracle.marginal(counter, keep, ts, shapes)
+    o32, o64 = api.marginal(dev(ts[0]), keep, others=[dev(t) for t in ts[1:]])
+    assert np.array_equal(host(o64), want)
+    assert np.array_equal(host(o32), want.astype(np.float32))
+    # real values: within the summation bound
+    tr = [rng.random(s).astype(np.float32) for s in shapes]
+    want = oracle.marginal(counter, keep, tr, shapes)
+    o32, o64 = api.marginal(dev(tr[0]), keep, others=[dev(t) for t in tr[1:]])
+    nred = int(np.prod([c for c, k in zip(counter, keep) if not k] or [1]))
+    assert np.all(np.abs(host(o64) - want) <= nred * EPS64 * np.abs(want) + 1e-300)
+
+
+# Short reduced runs (innermost, unit-stride, 4 .. 64 elements: a lane group
+# per output, one word quad per lane, butterflies): every run length, a
+# window of a wider operand, two operands, an output count that leaves the
+# last wave part empty.
+@pytest.mark.parametrize("shapes,keep", [
+    ([(70000, 4)], (1, 0)),
+    ([(40000, 8), (40000, 8)], (1, 0)),
+    ([(17000, 16)], (1, 0)),
+    ([(8193, 32)], (1, 0)),
+    ([(4099, 64)], (1, 0)),
+    ([(4100, 20), (4100, 16)], (1, 0)),
+    ([(5, 7, 1000, 16)], (1, 1, 1, 0)),
+])
+def test_marginal_short_runs(shapes, keep):
+    announce("marginal short runs", shapes, keep)
+    rng = inputs.rng(3, 27, len(shapes), int(np.prod(shapes[0])))
+    ts = [rng.integers(0, 5, size=s).astype(np.float32) for s in shapes]
+    counter = tuple(min(s[i] for s in shapes) for i in range(len(shapes[0])))
+    want = oracle.marginal(counter, keep, ts, shapes)
+    o32, o64 = api.marginal(dev(ts[0]), keep, others=[dev(t) for t in ts[1:]])
+    assert np.array_equal(host(o64), want)
+    assert np.array_equal(host(o32), want.astype(np.float32))
+    tr = [rng.random(s).astype(np.float32) for s in shapes]
+    want = oracle.marginal(counter, keep, tr, shapes)
+    o32, o64 = api.marginal(dev(tr[0]), keep, others=[dev(t) for t in tr[1:]])
+    nred = int(np.prod([c for c, k in zip(counter, keep) if not k] or [1]))
+    assert np.all(np.abs(host(o64) - want) <= nred * EPS64 * np.abs(want) + 1e-300)
+
+
 def test_marginal_integer_values_exact():
     announce("marginal exact")
     rng = np.random.default_rng(270)
