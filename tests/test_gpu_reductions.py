@@ -385,6 +385,34 @@ def test_conv_bit_exact(case):
     assert bits_equal(got, want), first_mismatch(got, want)
 
 
+# Signed zeros, subnormal products and overflow to +inf, bit for bit (no
+# invalid operation, so no NaN whose payload could differ between the host
+# and the GPU).
+@pytest.mark.parametrize("ls,rs", [((256, 8), (256, 8)), ((37,), (5,)), ((4, 6, 5), (3, 2, 7)),
+                                   ((100, 100), (5, 5))])
+def test_conv_signed_zeros_subnormals_overflow(ls, rs):
+    announce("conv special", ls, rs)
+    rng = np.random.default_rng(320 + len(ls))
+    l = rng.standard_normal(ls)
+    r = rng.standard_normal(rs)
+    lf, rf = l.reshape(-1), r.reshape(-1)
+    pick = rng.random(lf.size)
+    lf[pick < 0.3] = 0.0
+    lf[(pick >= 0.3) & (pick < 0.5)] = -0.0
+    lf[(pick >= 0.5) & (pick < 0.55)] = 1e-300
+    rf[rng.random(rf.size) < 0.2] = -0.0
+    rf[rng.random(rf.size) < 0.05] = 1e-20          # subnormal products with 1e-300
+    want = oracle.conv(np.ascontiguousarray(l), np.ascontiguousarray(r))
+    got = host(api.conv(dev(l), dev(r)))
+    assert bits_equal(got, want), first_mismatch(got, want)
+    # overflow: all-positive huge values sum to +inf
+    big_l = np.full(ls, 1e306)
+    big_r = np.abs(r) + 1.0
+    want = oracle.conv(big_l, np.ascontiguousarray(big_r))
+    got = host(api.conv(dev(big_l), dev(big_r)))
+    assert bits_equal(got, want), first_mismatch(got, want)
+
+
 def test_conv_rejects_bad_shapes_and_aliasing():
     announce("conv errors")
     l = torch.zeros((4, 5), dtype=torch.float64, device="cuda")
