@@ -84,6 +84,11 @@ __device__ __forceinline__ Seg seg_of(const SegPlan &P, uint64_t s)
     if (P.gdiv.c == 1) {
         g.row = s32;
         g.j0 = 0;
+    } else if (P.nseg <= 0xFFFFFFFFull) {
+        // fewer than 2^32 segments (uniform): 32-bit magic division by G
+        const uint32_t row = sdiv_u32(s32, P.gdiv);
+        g.row = row;
+        g.j0 = (s32 - row * P.G) * P.S;
     } else {
         // s < rows * G may exceed 32 bits only when G > 1; split it.
         uint64_t row = s / P.G;
