@@ -115,7 +115,7 @@ struct SegPlan {
     uint32_t rows;            // counter rows (< 2^32)
     uint32_t full;            // every operand contiguous over the counter
     uint32_t vec4;            // every operand contiguous along the row and L % 4 == 0
-    uint32_t stage;           // DOT, BBOX: full, vec4, L in {4, 8, 16}: tiles load through LDS
+    uint32_t stage;           // tiles load through LDS: 1 rows of 4, 8 or 16 words, 2 segments of 32
     uint32_t quads;           // DOT: one word quad per lane (vec4, quads < 2^31, not staged)
     AxisDiv qdiv;             // quads: quad -> (row, quad in row), divisor L / 4
     uint64_t nquads;          // quads: rows * L / 4

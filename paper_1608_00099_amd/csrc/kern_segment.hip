@@ -387,24 +387,23 @@ __device__ __forceinline__ void seg_moments(const SegPlan &P, const int64_t off[
 // (S == HALF, G == 1: uniform over the launch) no select is needed.  Fewer
 // registers than the running sums (the covariance instance of 6 axes: 126
 // VGPRs against 138), which lets the staged pass run 3 workgroups per CU.
-template <bool VEC, bool NTL, bool MULTI>
-__device__ __forceinline__ void seg_sums_fma(const SegPlan &P, const int64_t off[4], uint32_t len,
-                                             const HalfW<MULTI> &w0, double &s0, double &s1,
-                                             double &s2)
+template <bool MULTI>
+__device__ __forceinline__ void seg_sums_both(const SegPlan &P, uint32_t len, const HalfW<MULTI> &w0,
+                                              const HalfW<MULTI> &w1, double &s0, double &s1,
+                                              double &s2)
 {
     double a[2] = {0.0, 0.0}, b[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
-    const bool whole = P.S == (uint32_t)HALF && P.G == 1u;   // len == HALF everywhere
-    HalfW<MULTI> w1;
-    if (!whole && len > (uint32_t)HALF)
-        seg_load_half<VEC, NTL, MULTI>(P, off, len, HALF, w1);
+    // every segment S words long (uniform): a half wholly inside needs no select
+    const bool whole = P.L % P.S == 0u;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const uint32_t h0 = (uint32_t)(h * HALF);
-        if (h == 0 || (!whole && len > h0)) {
+        if (h == 0 || len > h0) {
             const HalfW<MULTI> &W = (h == 0) ? w0 : w1;
+            const bool plain = whole && P.S >= h0 + (uint32_t)HALF;
 #pragma unroll
             for (int j = 0; j < HALF; ++j) {
-                const double w = whole ? W.at(j) : W.at_or_zero(j, h0 + (uint32_t)j < len);
+                const double w = plain ? W.at(j) : W.at_or_zero(j, h0 + (uint32_t)j < len);
                 const int jj = h * HALF + j;
                 a[j & 1] += w;
                 b[j & 1] = fma((double)jj, w, b[j & 1]);
@@ -415,6 +414,17 @@ __device__ __forceinline__ void seg_sums_fma(const SegPlan &P, const int64_t off
     s0 = a[0] + a[1];
     s1 = b[0] + b[1];
     s2 = c[0] + c[1];
+}
+
+template <bool VEC, bool NTL, bool MULTI>
+__device__ __forceinline__ void seg_sums_fma(const SegPlan &P, const int64_t off[4], uint32_t len,
+                                             const HalfW<MULTI> &w0, double &s0, double &s1,
+                                             double &s2)
+{
+    HalfW<MULTI> w1;
+    if (len > (uint32_t)HALF)
+        seg_load_half<VEC, NTL, MULTI>(P, off, len, HALF, w1);
+    seg_sums_both<MULTI>(P, len, w0, w1, s0, s1, s2);
 }
 
 // Staged tile loads (plan flag `stage`: every operand contiguous over the
@@ -431,7 +441,11 @@ __device__ __forceinline__ void seg_sums_fma(const SegPlan &P, const int64_t off
 typedef float f4l __attribute__((ext_vector_type(4)));   // 16-byte aligned (LDS)
 constexpr int STG_ROW = 20;                              // LDS words per row at L = 16
 
-__device__ __forceinline__ uint32_t stg_row(uint32_t L) { return L == 4 ? 4u : (L == 8 ? 12u : 20u); }
+__device__ __forceinline__ uint32_t stg_row(uint32_t S)
+{
+    return S == 4 ? 4u : (S == 8 ? 12u : (S == 16 ? 20u : 36u));
+}
+constexpr int STG_ROW32 = 36;                            // LDS words per row at S = 32
 
 // Orders this wave's LDS accesses on both sides (no instruction: a wave's
 // LDS operations complete in order; this keeps the compiler from moving
@@ -453,29 +467,29 @@ __device__ __forceinline__ uint32_t stage_count(const SegPlan &P, uint64_t tile)
     return left < 64u ? (uint32_t)left : 64u;
 }
 
-__device__ __forceinline__ uint32_t stage_shift(uint32_t L)   // log2(quads per row)
+__device__ __forceinline__ uint32_t stage_shift(uint32_t S)   // log2(quads per segment)
 {
-    return L == 4 ? 0u : (L == 8 ? 1u : 2u);
+    return S == 4 ? 0u : (S == 8 ? 1u : (S == 16 ? 2u : 3u));
 }
 
 // The global loads of a staged tile of operand k: lane i takes quads
 // i, 64 + i, .. of the wave's range into x (indices clamped into the
 // range; the LDS pass drops the copies).
-template <bool NTL>
-__device__ __forceinline__ void stage_fetch(const SegPlan &P, int k, uint64_t tile, float x[HALF])
+template <bool NTL, int QN = HALF / 4>
+__device__ __forceinline__ void stage_fetch(const SegPlan &P, int k, uint64_t tile, float x[4 * QN])
 {
     const uint32_t cnt = stage_count(P, tile);
     if (cnt == 0u)
         return;
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t sh = stage_shift(P.L);
+    const uint32_t sh = stage_shift(P.S);
     const uint32_t nq = cnt << sh;
     const uint64_t s0 = tile * NT + (threadIdx.x & ~63u);
     const GLOBAL f4v *src =
         (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + P.base[k] +
-                             (int64_t)(s0 * P.L));
+                             (int64_t)(s0 * P.S));
 #pragma unroll
-    for (int i = 0; i < HALF / 4; ++i) {
+    for (int i = 0; i < QN; ++i) {
         if ((uint32_t)i < (1u << sh)) {
             const f4v y = ldg<NTL>(src + min((uint32_t)i * 64u + lane, nq - 1u));
             x[4 * i + 0] = y.x;
@@ -488,18 +502,19 @@ __device__ __forceinline__ void stage_fetch(const SegPlan &P, int k, uint64_t ti
 
 // Writes the fetched quads to the wave's LDS rows and reads this lane's
 // segment back into v[0..L).  Every lane of the wave takes part.
-__device__ __forceinline__ void stage_scatter(const SegPlan &P, uint64_t tile, const float x[HALF],
-                                              SHARED float *lds, float v[HALF])
+template <int QN = HALF / 4>
+__device__ __forceinline__ void stage_scatter(const SegPlan &P, uint64_t tile, const float x[4 * QN],
+                                              SHARED float *lds, float v[4 * QN])
 {
     const uint32_t cnt = stage_count(P, tile);
     if (cnt == 0u)
         return;
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t row = stg_row(P.L), sh = stage_shift(P.L);
+    const uint32_t row = stg_row(P.S), sh = stage_shift(P.S);
     const uint32_t nq = cnt << sh;
     wave_lds_sync();   // this wave's reads of the previous tile are done
 #pragma unroll
-    for (int i = 0; i < HALF / 4; ++i) {
+    for (int i = 0; i < QN; ++i) {
         const uint32_t q = (uint32_t)i * 64u + lane;
         if ((uint32_t)i < (1u << sh) && q < nq) {
             const uint32_t r = q >> sh, c = q & ((1u << sh) - 1u);
@@ -509,7 +524,7 @@ __device__ __forceinline__ void stage_scatter(const SegPlan &P, uint64_t tile, c
     wave_lds_sync();
     if (lane < cnt) {
 #pragma unroll
-        for (int i = 0; i < HALF / 4; ++i) {
+        for (int i = 0; i < QN; ++i) {
             if ((uint32_t)i < (1u << sh)) {
                 const f4l y = *(const SHARED f4l *)(lds + lane * row + 4u * (uint32_t)i);
                 v[4 * i + 0] = y.x;
@@ -556,6 +571,37 @@ __device__ __forceinline__ void stage_half(const SegPlan &P, uint64_t tile, SHAR
     }
 }
 
+// Segments of 32 words (S == 32, L a multiple of 32, every operand
+// contiguous over the counter): both halves of this lane's segment through
+// one staged pass (eight quads per lane; LDS rows of 36 words, an odd
+// number of quads).
+template <bool NTL, bool MULTI>
+__device__ __forceinline__ void stage_seg32(const SegPlan &P, uint64_t tile, SHARED float *lds,
+                                            HalfW<MULTI> &W0, HalfW<MULTI> &W1)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k == 0 || (MULTI && k < (int)P.n)) {
+            float x[SEG_MAX], v[SEG_MAX];
+            stage_fetch<NTL, SEG_MAX / 4>(P, k, tile, x);
+            stage_scatter<SEG_MAX / 4>(P, tile, x, lds, v);
+#pragma unroll
+            for (int j = 0; j < HALF; ++j) {
+                if constexpr (!MULTI) {
+                    W0.w[j] = v[j];
+                    W1.w[j] = v[HALF + j];
+                } else if (k == 0) {
+                    W0.w[j] = (double)v[j];
+                    W1.w[j] = (double)v[HALF + j];
+                } else {
+                    W0.w[j] *= (double)v[j];
+                    W1.w[j] *= (double)v[HALF + j];
+                }
+            }
+        }
+    }
+}
+
 // Element offsets of a segment's first element in every operand.
 template <int DM>
 __device__ __forceinline__ void seg_offsets(const SegPlan &P, const Seg &sg, int64_t off[4])
@@ -592,7 +638,9 @@ template <int DM, bool COV, bool MULTI> constexpr int moments_min_blocks()
     return 2;
 }
 
-template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true, bool STG = false>
+// STG: 0 per-lane segment loads; 1 staged tile loads of rows of 4, 8 or 16
+// words; 2 staged loads of 32-word segments (both halves).
+template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true, int STG = 0>
 __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void moments_kernel(const SegPlan plan)
 {
     SEG_PLAN_FOR(DM);
@@ -600,7 +648,8 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
     constexpr int T = TT::T;
     __shared__ double xch[8][NT];
     __shared__ double tot[T];
-    __shared__ __align__(16) float stg[STG ? NT / 64 : 1][STG ? 64 * STG_ROW : 4];
+    __shared__ __align__(16) float
+        stg[STG ? NT / 64 : 1][STG == 2 ? 64 * STG_ROW32 : (STG ? 64 * STG_ROW : 4)];
 
     double acc[T];
 #pragma unroll
@@ -617,8 +666,12 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
         const bool valid = s < P.nseg;
         Seg sg{0, 0, 0};
         int64_t off[4];
-        HalfW<MULTI> w0;
-        if constexpr (STG) {
+        HalfW<MULTI> w0, w1;
+        if constexpr (STG == 2) {
+            stage_seg32<NTL, MULTI>(P, tile, (SHARED float *)stg[threadIdx.x >> 6], w0, w1);
+            if (valid)
+                sg = seg_of(P, s);
+        } else if constexpr (STG == 1) {
             stage_half<NTL, MULTI>(P, tile, (SHARED float *)stg[threadIdx.x >> 6], w0);
             if (valid) {
                 sg = seg_of(P, s);
@@ -634,7 +687,10 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
             uint32_t tt[DM];
             row_coords<DM>(P, sg.row, u, tt);
             double s0, s1, s2;
-            seg_sums_fma<VEC, NTL, MULTI>(P, off, sg.len, w0, s0, s1, s2);
+            if constexpr (STG == 2)
+                seg_sums_both<MULTI>(P, sg.len, w0, w1, s0, s1, s2);
+            else
+                seg_sums_fma<VEC, NTL, MULTI>(P, off, sg.len, w0, s0, s1, s2);
             // inner axis: u_in = a + j with a = j0 - centre
             const double a = (double)sg.j0 - cin;
             const double A1 = fma(a, s0, s1);                       // sum w u_in
@@ -1282,13 +1338,19 @@ static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
     const bool multi = L.plan.n > 1;
     const bool cached = (L.plan.flags & TRIOT_MOMENTS_CACHED) != 0;
     const int k = (L.plan.vec4 ? 4 : 0) + (multi ? 2 : 0) + (cached ? 1 : 0);
-    if (L.plan.stage) {   // staged tile loads: an instance of their own (its LDS rows)
+    if (L.plan.stage == 1) {   // staged tile loads: instances of their own (their LDS rows)
         switch (k) {
-        case 7: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, false, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
-        case 6: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
-        case 5: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
-        case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 7: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, false, 1>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 6: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, true, 1>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 5: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false, 1>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, 1>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
         default: return hipErrorInvalidValue;   // the plan stages whole-quad rows only
+        }
+    } else if (L.plan.stage == 2) {   // one operand only (the plan's rule)
+        switch (k) {
+        case 5: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false, 2>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, 2>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        default: return hipErrorInvalidValue;
         }
     } else {
     switch (k) {
@@ -1400,18 +1462,19 @@ template <class K> static int occupancy(K kernel)
     return (e == hipSuccess && nb > 0) ? nb : 2;
 }
 
-template <int DM, bool COV> static int occ_moments(bool vec4, bool stage)
+template <int DM, bool COV> static int occ_moments(bool vec4, int stage)
 {
-    static int cache[3] = {0, 0, 0};
-    int &c = cache[stage ? 2 : (vec4 ? 1 : 0)];
+    static int cache[4] = {0, 0, 0, 0};
+    int &c = cache[stage ? 1 + stage : (vec4 ? 1 : 0)];
     if (!c)
-        c = stage  ? occupancy(moments_kernel<DM, COV, true, false, true, true>)
-            : vec4 ? occupancy(moments_kernel<DM, COV, true, false>)
-                   : occupancy(moments_kernel<DM, COV, false, false>);
+        c = stage == 2 ? occupancy(moments_kernel<DM, COV, true, false, true, 2>)
+            : stage    ? occupancy(moments_kernel<DM, COV, true, false, true, 1>)
+            : vec4     ? occupancy(moments_kernel<DM, COV, true, false>)
+                       : occupancy(moments_kernel<DM, COV, false, false>);
     return c;
 }
 
-int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4, bool stage)
+int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4, int stage)
 {
     if (adj) {
         static int cache[3] = {0, 0, 0};

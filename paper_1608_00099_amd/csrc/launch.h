@@ -26,7 +26,7 @@ struct BatchLaunch {
 hipError_t launch_batched(int co_op, BatchLaunch &B, hipStream_t st);
 hipError_t launch_moments(const SegLaunch &L, hipStream_t st);
 hipError_t launch_moments_adj(const SegLaunch &L, hipStream_t st);
-int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4, bool stage);
+int segment_blocks_per_cu(bool adj, bool cov, int dm, bool vec4, int stage);
 hipError_t launch_dot(const SegLaunch &L, hipStream_t st);
 hipError_t launch_bbox(const SegLaunch &L, hipStream_t st);
 hipError_t launch_conv(const ConvLaunch &L, hipStream_t st);

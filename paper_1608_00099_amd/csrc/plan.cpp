@@ -844,6 +844,10 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     const bool stage_moments = r.op == TRIOT_OP_MOMENTS && L == 16 && rows >= (int64_t(1) << 21);
     P.stage = (stage_rows && (r.op == TRIOT_OP_DOT || r.op == TRIOT_OP_BBOX || stage_moments))
                   ? 1u : 0u;
+    // Segments of 32 words laid end to end (rows a multiple of 32 words), one
+    // operand: the moments pass stages both halves of every segment.
+    if (r.op == TRIOT_OP_MOMENTS && n == 1 && full && vec4 && S == 32 && L % 32 == 0)
+        P.stage = 2u;
     // Inner product over other layouts of whole quads: one quad per lane, so
     // that the 8 lanes of a 32-word row load its 128 bytes together (with a
     // segment per lane, every load instruction touches 64 lines).
@@ -877,7 +881,7 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     const bool adj = r.op == TRIOT_OP_MOMENTS_ADJ;
     int bpc = 2;   // the inner product and the bounding box: 2 per CU
     if (r.op == TRIOT_OP_MOMENTS || adj)
-        bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4, P.stage != 0);
+        bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4, (int)P.stage);
     // (the staged moments pass: 3 per CU, measured faster on large inputs)
     if (!adj)
         bpc = std::min(bpc, (r.op == TRIOT_OP_MOMENTS && P.stage) ? 3 : 2);

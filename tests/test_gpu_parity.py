@@ -400,6 +400,27 @@ def test_moments_large_staged(shape):
         _check_moments(host(o32), host(o64), want, d, True)
 
 
+# Rows a multiple of 32 words laid end to end: the moments pass stages both
+# halves of every 32-word segment (one operand); segment counts below one
+# wave and ragged over several tiles; two operands keep per-lane loads.
+@pytest.mark.parametrize("shape", [(5, 32), (33, 7, 64), (256, 256), (3, 5, 7, 96), (64, 64, 64),
+                                   (1, 9, 1, 32)])
+def test_moments_32_word_segments(shape):
+    announce("moments 32-word segments", shape)
+    rng = inputs.rng(3, 28, len(shape), int(np.prod(shape)))
+    p = rng.gamma(0.5, 1.0, size=shape).astype(np.float32)
+    d = len(shape)
+    for cov in (True, False):
+        want = oracle.moments(shape, [p.reshape(-1)], [shape], cov=cov)
+        for cached in (False, True):
+            o32, o64 = api.moments(dev(p), cov=cov, cached=cached)
+            _check_moments(host(o32), host(o64), want, d, cov)
+    q = rng.random(shape, dtype=np.float32)
+    want = oracle.moments(shape, [p.reshape(-1), q.reshape(-1)], [shape, shape], cov=True)
+    o32, o64 = api.moments(dev(p), cov=True, others=[dev(q)])
+    _check_moments(host(o32), host(o64), want, d, True)
+
+
 @pytest.mark.parametrize("shape", STAGED_SHAPES)
 def test_dot_staged_rows(shape):
     announce("dot staged", shape)
