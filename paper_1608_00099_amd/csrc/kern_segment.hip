@@ -500,11 +500,11 @@ __device__ __forceinline__ void stage_fetch(const SegPlan &P, int k, uint64_t ti
     }
 }
 
-// Writes the fetched quads to the wave's LDS rows and reads this lane's
-// segment back into v[0..L).  Every lane of the wave takes part.
+// Writes the fetched quads to the wave's LDS rows.  Every lane of the
+// wave takes part.
 template <int QN = HALF / 4>
-__device__ __forceinline__ void stage_scatter(const SegPlan &P, uint64_t tile, const float x[4 * QN],
-                                              SHARED float *lds, float v[4 * QN])
+__device__ __forceinline__ void stage_put(const SegPlan &P, uint64_t tile, const float x[4 * QN],
+                                          SHARED float *lds)
 {
     const uint32_t cnt = stage_count(P, tile);
     if (cnt == 0u)
@@ -522,18 +522,39 @@ __device__ __forceinline__ void stage_scatter(const SegPlan &P, uint64_t tile, c
         }
     }
     wave_lds_sync();
-    if (lane < cnt) {
+}
+
+// Reads quads Q0 .. Q0 + QN - 1 of this lane's segment back from the
+// wave's LDS rows into v (lanes past the last segment read nothing).
+template <int QN = HALF / 4, int Q0 = 0>
+__device__ __forceinline__ void stage_get(const SegPlan &P, uint64_t tile, const SHARED float *lds,
+                                          float v[4 * QN])
+{
+    const uint32_t cnt = stage_count(P, tile);
+    const uint32_t lane = threadIdx.x & 63u;
+    if (lane >= cnt)
+        return;
+    const uint32_t row = stg_row(P.S), sh = stage_shift(P.S);
 #pragma unroll
-        for (int i = 0; i < QN; ++i) {
-            if ((uint32_t)i < (1u << sh)) {
-                const f4l y = *(const SHARED f4l *)(lds + lane * row + 4u * (uint32_t)i);
-                v[4 * i + 0] = y.x;
-                v[4 * i + 1] = y.y;
-                v[4 * i + 2] = y.z;
-                v[4 * i + 3] = y.w;
-            }
+    for (int i = 0; i < QN; ++i) {
+        if ((uint32_t)(Q0 + i) < (1u << sh)) {
+            const f4l y = *(const SHARED f4l *)(lds + lane * row + 4u * (uint32_t)(Q0 + i));
+            v[4 * i + 0] = y.x;
+            v[4 * i + 1] = y.y;
+            v[4 * i + 2] = y.z;
+            v[4 * i + 3] = y.w;
         }
     }
+}
+
+// Writes the fetched quads to the wave's LDS rows and reads this lane's
+// segment back into v.  Every lane of the wave takes part.
+template <int QN = HALF / 4>
+__device__ __forceinline__ void stage_scatter(const SegPlan &P, uint64_t tile, const float x[4 * QN],
+                                              SHARED float *lds, float v[4 * QN])
+{
+    stage_put<QN>(P, tile, x, lds);
+    stage_get<QN, 0>(P, tile, lds, v);
 }
 
 template <bool NTL>
@@ -1156,11 +1177,11 @@ __device__ __forceinline__ uint32_t seg_nonzero_half(const SegPlan &P, const int
 }
 
 template <int DM, bool VEC, bool NTL = true>
-__global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPlan plan)
+__global__ __launch_bounds__(NT, 2) void bbox_kernel(const SegPlan plan)
 {
     SEG_PLAN_FOR(DM);
     __shared__ uint32_t slo[DM], shi[DM];
-    __shared__ __align__(16) float stg[VEC ? NT / 64 : 1][VEC ? 64 * STG_ROW : 4];
+    __shared__ __align__(16) float stg[VEC ? NT / 64 : 1][VEC ? 64 * STG_ROW32 : 4];
     const int D = (int)P.D;
     uint32_t lo[DM], hi[DM];
 #pragma unroll
@@ -1176,8 +1197,8 @@ __global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPl
     const uint64_t g = gridDim.x;
     for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
         const uint64_t s = tile * NT + threadIdx.x;
-        uint32_t staged = 0xFFFFu;   // staged tiles: the nonzero mask of the segment
-        if (VEC && P.stage) {
+        uint32_t staged = 0xFFFFFFFFu;   // staged tiles: the nonzero mask of the segment
+        if (VEC && P.stage == 1) {
             SHARED float *lds = (SHARED float *)stg[threadIdx.x >> 6];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -1191,6 +1212,28 @@ __global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPl
                     staged &= mk;
                 }
             }
+        } else if (VEC && P.stage == 2) {
+            // segments of 32 words laid end to end: both halves at once
+            SHARED float *lds = (SHARED float *)stg[threadIdx.x >> 6];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < (int)P.n) {
+                    float x[SEG_MAX];
+                    stage_fetch<NTL, SEG_MAX / 4>(P, k, tile, x);
+                    stage_put<SEG_MAX / 4>(P, tile, x, lds);
+                    float v[HALF];
+                    uint32_t mk = 0;
+                    stage_get<HALF / 4, 0>(P, tile, lds, v);
+#pragma unroll
+                    for (int j = 0; j < HALF; ++j)
+                        mk |= (v[j] != 0.0f ? 1u : 0u) << j;
+                    stage_get<HALF / 4, HALF / 4>(P, tile, lds, v);
+#pragma unroll
+                    for (int j = 0; j < HALF; ++j)
+                        mk |= (v[j] != 0.0f ? 1u : 0u) << (HALF + j);
+                    staged &= mk;
+                }
+            }
         }
         if (s < P.nseg) {
             const Seg sg = seg_of(P, s);
@@ -1198,7 +1241,7 @@ __global__ __launch_bounds__(NT, (DM <= 8 ? 4 : 2)) void bbox_kernel(const SegPl
             seg_offsets<DM>(P, sg, off);
             uint32_t m;
             if (VEC && P.stage) {
-                m = staged & ((1u << sg.len) - 1u);   // len <= 16
+                m = sg.len >= 32u ? staged : staged & ((1u << sg.len) - 1u);
             } else {
                 m = seg_nonzero_half<VEC, NTL>(P, off, sg.len, 0);
                 if (sg.len > (uint32_t)HALF)

@@ -844,9 +844,11 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     const bool stage_moments = r.op == TRIOT_OP_MOMENTS && L == 16 && rows >= (int64_t(1) << 21);
     P.stage = (stage_rows && (r.op == TRIOT_OP_DOT || r.op == TRIOT_OP_BBOX || stage_moments))
                   ? 1u : 0u;
-    // Segments of 32 words laid end to end (rows a multiple of 32 words), one
-    // operand: the moments pass stages both halves of every segment.
-    if (r.op == TRIOT_OP_MOMENTS && n == 1 && full && vec4 && S == 32 && L % 32 == 0)
+    // Segments of 32 words laid end to end (rows a multiple of 32 words):
+    // the moments pass (one operand) and the bounding box stage both halves
+    // of every segment.
+    if (((r.op == TRIOT_OP_MOMENTS && n == 1) || r.op == TRIOT_OP_BBOX) && full && vec4 &&
+        S == 32 && L % 32 == 0)
         P.stage = 2u;
     // Inner product over other layouts of whole quads: one quad per lane, so
     // that the 8 lanes of a 32-word row load its 128 bytes together (with a

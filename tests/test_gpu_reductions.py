@@ -345,6 +345,30 @@ def test_bbox_short_rows(shape, density):
         assert np.array_equal(got, want), (corner, got, want)
 
 
+# Rows a multiple of 32 words laid end to end: both halves of every 32-word
+# segment through one staged pass; one and two operands, single nonzeros at
+# the first and last point and inside the second half of a segment.
+@pytest.mark.parametrize("shape", [(5, 32), (33, 7, 64), (256, 256), (3, 5, 7, 96)])
+def test_bbox_32_word_segments(shape):
+    announce("bbox 32-word segments", shape)
+    rng = inputs.rng(3, 29, len(shape), int(np.prod(shape)))
+    a = rng.standard_normal(shape).astype(np.float32)
+    b = rng.standard_normal(shape).astype(np.float32)
+    a[rng.random(shape) >= 0.01] = 0.0
+    b[rng.random(shape) >= 0.5] = 0.0
+    for ts in ([a], [a, b]):
+        want = oracle.bbox(shape, ts, [shape] * len(ts))
+        got = host(api.bbox(*[dev(t) for t in ts]))
+        assert np.array_equal(got, want), (got, want)
+    n = int(np.prod(shape))
+    for idx in (0, n - 1, 21, n - 7):
+        c = np.zeros(shape, np.float32)
+        c.reshape(-1)[idx] = -2.0
+        want = oracle.bbox(shape, [c], [shape])
+        got = host(api.bbox(dev(c)))
+        assert np.array_equal(got, want), (idx, got, want)
+
+
 def test_bbox_special_values_and_underflowing_products():
     announce("bbox special")
     a = np.zeros((6, 70), np.float32)
