@@ -548,13 +548,40 @@ __device__ __forceinline__ void stage_get(const SegPlan &P, uint64_t tile, const
 }
 
 // Writes the fetched quads to the wave's LDS rows and reads this lane's
-// segment back into v.  Every lane of the wave takes part.
+// segment back into v (stage_put and stage_get in one pass).  Every lane of
+// the wave takes part.
 template <int QN = HALF / 4>
 __device__ __forceinline__ void stage_scatter(const SegPlan &P, uint64_t tile, const float x[4 * QN],
                                               SHARED float *lds, float v[4 * QN])
 {
-    stage_put<QN>(P, tile, x, lds);
-    stage_get<QN, 0>(P, tile, lds, v);
+    const uint32_t cnt = stage_count(P, tile);
+    if (cnt == 0u)
+        return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t row = stg_row(P.S), sh = stage_shift(P.S);
+    const uint32_t nq = cnt << sh;
+    wave_lds_sync();   // this wave's reads of the previous tile are done
+#pragma unroll
+    for (int i = 0; i < QN; ++i) {
+        const uint32_t q = (uint32_t)i * 64u + lane;
+        if ((uint32_t)i < (1u << sh) && q < nq) {
+            const uint32_t r = q >> sh, c = q & ((1u << sh) - 1u);
+            *(SHARED f4l *)(lds + r * row + 4u * c) = f4l{x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]};
+        }
+    }
+    wave_lds_sync();
+    if (lane < cnt) {
+#pragma unroll
+        for (int i = 0; i < QN; ++i) {
+            if ((uint32_t)i < (1u << sh)) {
+                const f4l y = *(const SHARED f4l *)(lds + lane * row + 4u * (uint32_t)i);
+                v[4 * i + 0] = y.x;
+                v[4 * i + 1] = y.y;
+                v[4 * i + 2] = y.z;
+                v[4 * i + 3] = y.w;
+            }
+        }
+    }
 }
 
 template <bool NTL>
@@ -1176,12 +1203,15 @@ __device__ __forceinline__ uint32_t seg_nonzero_half(const SegPlan &P, const int
     return m;
 }
 
-template <int DM, bool VEC, bool NTL = true>
-__global__ __launch_bounds__(NT, 2) void bbox_kernel(const SegPlan plan)
+// W32: the instance for staged 32-word segments (its LDS rows and
+// registers: 2 workgroups per CU, the number the plan runs).
+template <int DM, bool VEC, bool NTL = true, bool W32 = false>
+__global__ __launch_bounds__(NT, (W32 || DM > 8) ? 2 : 4) void bbox_kernel(const SegPlan plan)
 {
     SEG_PLAN_FOR(DM);
     __shared__ uint32_t slo[DM], shi[DM];
-    __shared__ __align__(16) float stg[VEC ? NT / 64 : 1][VEC ? 64 * STG_ROW32 : 4];
+    __shared__ __align__(16) float
+        stg[VEC ? NT / 64 : 1][W32 ? 64 * STG_ROW32 : (VEC ? 64 * STG_ROW : 4)];
     const int D = (int)P.D;
     uint32_t lo[DM], hi[DM];
 #pragma unroll
@@ -1198,7 +1228,7 @@ __global__ __launch_bounds__(NT, 2) void bbox_kernel(const SegPlan plan)
     for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
         const uint64_t s = tile * NT + threadIdx.x;
         uint32_t staged = 0xFFFFFFFFu;   // staged tiles: the nonzero mask of the segment
-        if (VEC && P.stage == 1) {
+        if (VEC && !W32 && P.stage == 1) {
             SHARED float *lds = (SHARED float *)stg[threadIdx.x >> 6];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -1212,7 +1242,7 @@ __global__ __launch_bounds__(NT, 2) void bbox_kernel(const SegPlan plan)
                     staged &= mk;
                 }
             }
-        } else if (VEC && P.stage == 2) {
+        } else if constexpr (W32) {
             // segments of 32 words laid end to end: both halves at once
             SHARED float *lds = (SHARED float *)stg[threadIdx.x >> 6];
 #pragma unroll
@@ -1462,14 +1492,19 @@ hipError_t launch_dot(const SegLaunch &L, hipStream_t st)
 
 hipError_t launch_bbox(const SegLaunch &L, hipStream_t st)
 {
+    const bool w32 = L.plan.stage == 2;   // staged 32-word segments (vec4 implied)
     if (L.dm <= 8) {
-        if (L.plan.vec4)
+        if (w32)
+            hipLaunchKernelGGL((bbox_kernel<8, true, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        else if (L.plan.vec4)
             hipLaunchKernelGGL((bbox_kernel<8, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
         else
             hipLaunchKernelGGL((bbox_kernel<8, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
         hipLaunchKernelGGL((bbox_final_kernel<8>), dim3(1), dim3(FNT), 0, st, L.plan);
     } else {
-        if (L.plan.vec4)
+        if (w32)
+            hipLaunchKernelGGL((bbox_kernel<32, true, true, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        else if (L.plan.vec4)
             hipLaunchKernelGGL((bbox_kernel<32, true>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
         else
             hipLaunchKernelGGL((bbox_kernel<32, false>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
