@@ -686,8 +686,160 @@ template <int DM, bool COV, bool MULTI> constexpr int moments_min_blocks()
     return 2;
 }
 
+// Folds one segment's sums (s0, s1, s2 along the inner axis) into the
+// accumulators: the outer coordinates enter once per segment.
+template <int DM, bool COV>
+__device__ __forceinline__ void seg_fold(const SegPlan &P, const Seg &sg, double s0, double s1,
+                                         double s2, double cin, double *acc)
+{
+    typedef Terms<DM, COV> TT;
+    double u[DM];
+    uint32_t tt[DM];
+    row_coords<DM>(P, sg.row, u, tt);
+    // inner axis: u_in = a + j with a = j0 - centre
+    const double a = (double)sg.j0 - cin;
+    const double A1 = fma(a, s0, s1);                       // sum w u_in
+    acc[0] += s0;
+    acc[TT::K + 0] += A1;
+#pragma unroll
+    for (int p = 1; p < DM; ++p)
+        acc[TT::K + p] = fma(u[p], s0, acc[TT::K + p]);
+    if constexpr (COV) {
+        const double A2 = fma(a, fma(a, s0, 2.0 * s1), s2);  // sum w u_in^2
+        acc[TT::c(0, 0)] += A2;
+#pragma unroll
+        for (int p = 1; p < DM; ++p)
+            acc[TT::c(0, p)] = fma(u[p], A1, acc[TT::c(0, p)]);
+#pragma unroll
+        for (int q = 1; q < DM; ++q) {
+            const double uq = u[q] * s0;
+#pragma unroll
+            for (int p = 1; p <= q; ++p)
+                acc[TT::c(p, q)] = fma(u[p], uq, acc[TT::c(p, q)]);
+        }
+    }
+}
+
+// Row blocks (rows of LL = 2, 4 or 8 words laid end to end): a segment of
+// 16 words holds 16 / LL whole rows, which differ only in the next axis
+// (position 1; the plan makes its extent a multiple of 16 / LL).  With
+// ja = j % LL and jb = j / LL the segment gives S0 = sum w, Sa = sum ja w,
+// Saa = sum ja^2 w, Sb = sum jb w, Sbb = sum jb^2 w and Sab = sum ja jb w
+// (compile-time multipliers; the second moments only with COV).
+template <int LL, bool COV>
+__device__ __forceinline__ void rowblock_sums(const float v[16], double S[6])
+{
+    double acc[6][2] = {};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int ja = j % LL, jb = j / LL;
+        const double w = (double)v[j];
+        acc[0][j & 1] += w;
+        acc[1][j & 1] = fma((double)ja, w, acc[1][j & 1]);
+        acc[3][j & 1] = fma((double)jb, w, acc[3][j & 1]);
+        if constexpr (COV) {
+            acc[2][j & 1] = fma((double)(ja * ja), w, acc[2][j & 1]);
+            acc[4][j & 1] = fma((double)(jb * jb), w, acc[4][j & 1]);
+            acc[5][j & 1] = fma((double)(ja * jb), w, acc[5][j & 1]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        S[i] = acc[i][0] + acc[i][1];
+}
+
+// Folds a row block: positions 0 (inner) and 1 (the next axis, from the
+// block's first row) from the block sums, the outer positions once.
+template <int DM, bool COV>
+__device__ __forceinline__ void rowblock_fold(const SegPlan &P, uint32_t row, const double S[6],
+                                              double cin, double *acc)
+{
+    typedef Terms<DM, COV> TT;
+    double u[DM];
+    uint32_t tt[DM];
+    row_coords<DM>(P, row, u, tt);
+    const double a = -cin, b = u[1];
+    const double A1 = fma(a, S[0], S[1]);   // sum w u_0
+    const double B1 = fma(b, S[0], S[3]);   // sum w u_1
+    acc[0] += S[0];
+    acc[TT::K + 0] += A1;
+    acc[TT::K + 1] += B1;
+#pragma unroll
+    for (int p = 2; p < DM; ++p)
+        acc[TT::K + p] = fma(u[p], S[0], acc[TT::K + p]);
+    if constexpr (COV) {
+        acc[TT::c(0, 0)] += fma(a, fma(a, S[0], 2.0 * S[1]), S[2]);   // sum w u_0^2
+        acc[TT::c(1, 1)] += fma(b, fma(b, S[0], 2.0 * S[3]), S[4]);   // sum w u_1^2
+        acc[TT::c(0, 1)] += fma(a, B1, fma(b, S[1], S[5]));          // sum w u_0 u_1
+#pragma unroll
+        for (int p = 2; p < DM; ++p) {
+            acc[TT::c(0, p)] = fma(u[p], A1, acc[TT::c(0, p)]);
+            acc[TT::c(1, p)] = fma(u[p], B1, acc[TT::c(1, p)]);
+        }
+#pragma unroll
+        for (int q = 2; q < DM; ++q) {
+            const double uq = u[q] * S[0];
+#pragma unroll
+            for (int p = 2; p <= q; ++p)
+                acc[TT::c(p, q)] = fma(u[p], uq, acc[TT::c(p, q)]);
+        }
+    }
+}
+
+// Short segments (rows of at most 8 words, one operand): a segment per lane
+// is a single small load, so a loop of one tile at a time waits out a full
+// memory round trip per handful of words.  Here every lane loads its
+// segments of SHORT_TILES consecutive tiles first (half as many in the
+// 32-axis tier; at most two 16-byte loads, or eight words, each), then
+// folds them in tile order.
+constexpr int SHORT_TILES = 8;
+constexpr int SHORT_W = 8;
+
+template <bool VEC, bool NTL>
+__device__ __forceinline__ void short_load(const SegPlan &P, const int64_t off[4], uint32_t len,
+                                           float v[SHORT_W])
+{
+    const GLOBAL float *p0 = (const GLOBAL float *)(uintptr_t)P.ptr[0] + off[0];
+    if constexpr (VEC) {
+        const uint32_t qmax = (len >> 2) - 1;
+#pragma unroll
+        for (int q = 0; q < SHORT_W / 4; ++q) {
+            const f4v x = ldg<NTL>((const GLOBAL f4v *)p0 + min((uint32_t)q, qmax));
+            v[4 * q + 0] = x.x;
+            v[4 * q + 1] = x.y;
+            v[4 * q + 2] = x.z;
+            v[4 * q + 3] = x.w;
+        }
+    } else {
+        const int64_t ik = P.stride[0][P.D - 1];
+#pragma unroll
+        for (int j = 0; j < SHORT_W; ++j)
+            v[j] = ldg<NTL>(p0 + (int64_t)min((uint32_t)j, len - 1) * ik);
+    }
+}
+
+// Sums of a short segment over its local coordinate j: w, j w, j^2 w
+// (words past len enter as zero).
+__device__ __forceinline__ void short_sums(uint32_t len, const float v[SHORT_W], double &s0,
+                                           double &s1, double &s2)
+{
+    double a[2] = {0.0, 0.0}, b[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < SHORT_W; ++j) {
+        const double w = (double)((uint32_t)j < len ? v[j] : 0.0f);
+        a[j & 1] += w;
+        b[j & 1] = fma((double)j, w, b[j & 1]);
+        c[j & 1] = fma((double)(j * j), w, c[j & 1]);
+    }
+    s0 = a[0] + a[1];
+    s1 = b[0] + b[1];
+    s2 = c[0] + c[1];
+}
+
 // STG: 0 per-lane segment loads; 1 staged tile loads of rows of 4, 8 or 16
-// words; 2 staged loads of 32-word segments (both halves).
+// words; 2 staged loads of 32-word segments (both halves); 3 short segments
+// (at most 8 words, one operand), SHORT_TILES tiles per pass; 4 row blocks
+// (16-word segments of whole short rows, staged).
 template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true, int STG = 0>
 __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void moments_kernel(const SegPlan plan)
 {
@@ -697,7 +849,8 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
     __shared__ double xch[8][NT];
     __shared__ double tot[T];
     __shared__ __align__(16) float
-        stg[STG ? NT / 64 : 1][STG == 2 ? 64 * STG_ROW32 : (STG ? 64 * STG_ROW : 4)];
+        stg[(STG == 1 || STG == 2 || STG == 4) ? NT / 64 : 1]
+           [STG == 2 ? 64 * STG_ROW32 : ((STG == 1 || STG == 4) ? 64 * STG_ROW : 4)];
 
     double acc[T];
 #pragma unroll
@@ -709,6 +862,53 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
     const uint32_t lb = seg_logical_block();
     const uint64_t g = gridDim.x;
 
+    if constexpr (STG == 4) {
+        SHARED float *lds = (SHARED float *)stg[threadIdx.x >> 6];
+        for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
+            const uint64_t s = tile * NT + threadIdx.x;
+            float v[16];
+            stage_words<NTL>(P, 0, tile, lds, v);
+            if (s < P.nseg) {
+                double S[6];
+                if (P.L == 2)
+                    rowblock_sums<2, COV>(v, S);
+                else if (P.L == 4)
+                    rowblock_sums<4, COV>(v, S);
+                else
+                    rowblock_sums<8, COV>(v, S);
+                rowblock_fold<DM, COV>(P, (uint32_t)s * P.rb, S, cin, acc);
+            }
+        }
+    } else if constexpr (STG == 3) {
+        // block lb takes tiles lb*K .. lb*K + K-1, then (lb + g)*K .. (K
+        // halved for the 32-axis tier: its accumulators leave fewer registers)
+        constexpr int K = DM > 8 ? SHORT_TILES / 2 : SHORT_TILES;
+        for (uint64_t t0 = (uint64_t)lb * K; t0 < P.ntiles; t0 += g * K) {
+            float v[K][SHORT_W];
+            Seg sg[K];
+            bool ok[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint64_t s = (t0 + (uint64_t)k) * NT + threadIdx.x;
+                ok[k] = t0 + (uint64_t)k < P.ntiles && s < P.nseg;
+                sg[k] = Seg{0, 0, 0};
+                if (ok[k]) {
+                    int64_t off[4];
+                    sg[k] = seg_of(P, s);
+                    seg_offsets<DM>(P, sg[k], off);
+                    short_load<VEC, NTL>(P, off, sg[k].len, v[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (ok[k]) {
+                    double s0, s1, s2;
+                    short_sums(sg[k].len, v[k], s0, s1, s2);
+                    seg_fold<DM, COV>(P, sg[k], s0, s1, s2, cin, acc);
+                }
+            }
+        }
+    } else {
     for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
         const uint64_t s = tile * NT + threadIdx.x;
         const bool valid = s < P.nseg;
@@ -731,37 +931,14 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
             seg_load_half<VEC, NTL, MULTI>(P, off, sg.len, 0, w0);
         }
         if (valid) {
-            double u[DM];
-            uint32_t tt[DM];
-            row_coords<DM>(P, sg.row, u, tt);
             double s0, s1, s2;
             if constexpr (STG == 2)
                 seg_sums_both<MULTI>(P, sg.len, w0, w1, s0, s1, s2);
             else
                 seg_sums_fma<VEC, NTL, MULTI>(P, off, sg.len, w0, s0, s1, s2);
-            // inner axis: u_in = a + j with a = j0 - centre
-            const double a = (double)sg.j0 - cin;
-            const double A1 = fma(a, s0, s1);                       // sum w u_in
-            acc[0] += s0;
-            acc[TT::K + 0] += A1;
-#pragma unroll
-            for (int p = 1; p < DM; ++p)
-                acc[TT::K + p] = fma(u[p], s0, acc[TT::K + p]);
-            if constexpr (COV) {
-                const double A2 = fma(a, fma(a, s0, 2.0 * s1), s2);  // sum w u_in^2
-                acc[TT::c(0, 0)] += A2;
-#pragma unroll
-                for (int p = 1; p < DM; ++p)
-                    acc[TT::c(0, p)] = fma(u[p], A1, acc[TT::c(0, p)]);
-#pragma unroll
-                for (int q = 1; q < DM; ++q) {
-                    const double uq = u[q] * s0;
-#pragma unroll
-                    for (int p = 1; p <= q; ++p)
-                        acc[TT::c(p, q)] = fma(u[p], uq, acc[TT::c(p, q)]);
-                }
-            }
+            seg_fold<DM, COV>(P, sg, s0, s1, s2, cin, acc);
         }
+    }
     }
 
     // ---- workgroup reduction (fixed order) ----
@@ -1419,6 +1596,23 @@ static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
         case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, 1>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
         default: return hipErrorInvalidValue;   // the plan stages whole-quad rows only
         }
+    } else if (L.plan.stage == 4) {   // row blocks, one operand, two axes or more (the plan's rule)
+        if constexpr (DM >= 2) {
+            if (cached)
+                hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false, 4>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+            else
+                hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, 4>), dim3(L.blocks), dim3(NT), 0, st, L.plan);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (L.plan.stage == 3) {   // short segments, one operand (the plan's rule)
+        switch (k) {
+        case 5: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false, 3>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, 3>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 1: hipLaunchKernelGGL((moments_kernel<DM, COV, false, false, false, 3>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 0: hipLaunchKernelGGL((moments_kernel<DM, COV, false, false, true, 3>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        default: return hipErrorInvalidValue;
+        }
     } else if (L.plan.stage == 2) {   // one operand only (the plan's rule)
         switch (k) {
         case 5: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false, 2>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
@@ -1542,13 +1736,27 @@ template <class K> static int occupancy(K kernel)
 
 template <int DM, bool COV> static int occ_moments(bool vec4, int stage)
 {
-    static int cache[4] = {0, 0, 0, 0};
-    int &c = cache[stage ? 1 + stage : (vec4 ? 1 : 0)];
-    if (!c)
-        c = stage == 2 ? occupancy(moments_kernel<DM, COV, true, false, true, 2>)
-            : stage    ? occupancy(moments_kernel<DM, COV, true, false, true, 1>)
-            : vec4     ? occupancy(moments_kernel<DM, COV, true, false>)
-                       : occupancy(moments_kernel<DM, COV, false, false>);
+    static int cache[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+    int &c = cache[vec4 ? 1 : 0][stage < 5 ? stage : 0];
+    if (!c) {
+        switch (stage) {
+        case 4:
+            if constexpr (DM >= 2)
+                c = occupancy(moments_kernel<DM, COV, true, false, true, 4>);
+            else
+                c = 2;
+            break;
+        case 1: c = occupancy(moments_kernel<DM, COV, true, false, true, 1>); break;
+        case 2: c = occupancy(moments_kernel<DM, COV, true, false, true, 2>); break;
+        case 3:
+            c = vec4 ? occupancy(moments_kernel<DM, COV, true, false, true, 3>)
+                     : occupancy(moments_kernel<DM, COV, false, false, true, 3>);
+            break;
+        default:
+            c = vec4 ? occupancy(moments_kernel<DM, COV, true, false>)
+                     : occupancy(moments_kernel<DM, COV, false, false>);
+        }
+    }
     return c;
 }
 

@@ -850,6 +850,22 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     if (((r.op == TRIOT_OP_MOMENTS && n == 1) || r.op == TRIOT_OP_BBOX) && full && vec4 &&
         S == 32 && L % 32 == 0)
         P.stage = 2u;
+    // Rows of at most 8 words, one operand, any layout: the moments pass
+    // loads the segments of several tiles before folding them.
+    if (r.op == TRIOT_OP_MOMENTS && n == 1 && L <= 8 && !P.stage)
+        P.stage = 3u;
+    // Rows of 2, 4 or 8 words laid end to end, one operand, the next axis a
+    // multiple of 16 / L: the moments pass takes segments of 16 / L whole
+    // rows (16 words), so that the outer coordinates enter once per 16
+    // words instead of once per row.
+    if (r.op == TRIOT_OP_MOMENTS && n == 1 && full && D >= 2 && (L == 2 || L == 4 || L == 8) &&
+        c[D - 2] % (16 / L) == 0) {
+        P.stage = 4u;
+        P.rb = (uint32_t)(16 / L);
+        P.S = 16;
+        P.nseg = (uint64_t)rows / P.rb;
+        P.ntiles = (P.nseg + NT - 1) / NT;
+    }
     // Inner product over other layouts of whole quads: one quad per lane, so
     // that the 8 lanes of a 32-word row load its 128 bytes together (with a
     // segment per lane, every load instruction touches 64 lines).
@@ -886,7 +902,7 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
         bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4, (int)P.stage);
     // (the staged moments pass: 3 per CU, measured faster on large inputs)
     if (!adj)
-        bpc = std::min(bpc, (r.op == TRIOT_OP_MOMENTS && P.stage) ? 3 : 2);
+        bpc = std::min(bpc, (r.op == TRIOT_OP_MOMENTS && (P.stage == 1 || P.stage == 2 || P.stage == 4)) ? 3 : 2);
     int64_t blocks = std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * bpc);
     if (blocks > 8)
         blocks = (blocks + 7) / 8 * 8;

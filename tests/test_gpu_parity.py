@@ -421,6 +421,44 @@ def test_moments_32_word_segments(shape):
     _check_moments(host(o32), host(o64), want, d, True)
 
 
+# Rows of at most 8 words, one operand: the moments pass loads the segments
+# of several tiles before folding them.  Many small axes (both accumulator
+# tiers), an inner extent that is not whole quads, and a window.
+# (Rows of 2, 4 or 8 words laid end to end whose next axis is a multiple of
+# 16 / L take 16-word row blocks instead: 4^12, 8^8, (3, 16, 2), (5, 12, 4),
+# (7, 6, 8), (16^5, 4, 4).)
+@pytest.mark.parametrize("shape,cov", [((4,) * 12, False), ((8,) * 8, True), ((3, 1000, 3), True),
+                                       ((6, 5, 7, 6, 5, 7), True), ((2,) * 20, False),
+                                       ((3, 16, 2), True), ((5, 12, 4), True), ((7, 6, 8), True),
+                                       ((16, 16, 16, 16, 16, 4, 4), True), ((4,) * 8, False),
+                                       ((9, 7, 8), True)])
+def test_moments_short_rows_batched(shape, cov):
+    announce("moments short rows batched", shape, cov)
+    rng = inputs.rng(3, 30, len(shape), int(np.prod(shape)))
+    p = rng.random(shape, dtype=np.float32)
+    d = len(shape)
+    want = oracle.moments(shape, [p.reshape(-1)], [shape], cov=cov)
+    for cached in (False, True):
+        o32, o64 = api.moments(dev(p), cov=cov, cached=cached)
+        _check_moments(host(o32), host(o64), want, d, cov)
+
+
+def test_moments_short_rows_window():
+    announce("moments short rows window")
+    rng = inputs.rng(3, 31)
+    parent = (40, 50, 9)
+    P = rng.random(parent, dtype=np.float32)
+    base = int(np.ravel_multi_index((3, 2, 1), parent))
+    counter = (33, 47, 7)
+    want = oracle.moments(counter, [P.reshape(-1)], [parent], bases=[base])
+    out32 = torch.empty(1 + 3 + 6, device="cuda")
+    out64 = torch.empty(1 + 3 + 6, dtype=torch.float64, device="cuda")
+    ws = api.workspace_for(L.OP_MOMENTS, [parent], counter, torch.device("cuda"))
+    params = L.MomentsParams(L.MOMENTS_FIRST | L.MOMENTS_COV, out64.data_ptr())
+    api.apply(L.OP_MOMENTS, [dev(P)], [parent], counter, [base], params, out=out32, workspace=ws)
+    _check_moments(host(out32), host(out64), want, 3, True)
+
+
 @pytest.mark.parametrize("shape", STAGED_SHAPES)
 def test_dot_staged_rows(shape):
     announce("dot staged", shape)
