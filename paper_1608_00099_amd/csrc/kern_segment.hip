@@ -416,15 +416,35 @@ __device__ __forceinline__ void seg_sums_both(const SegPlan &P, uint32_t len, co
     s2 = c[0] + c[1];
 }
 
-template <bool VEC, bool NTL, bool MULTI>
+// WHOLE: every segment is exactly HALF words (S == HALF, G == 1), known at
+// compile time: the instance carries no second-half path.
+template <bool VEC, bool NTL, bool MULTI, bool WHOLE = false>
 __device__ __forceinline__ void seg_sums_fma(const SegPlan &P, const int64_t off[4], uint32_t len,
                                              const HalfW<MULTI> &w0, double &s0, double &s1,
                                              double &s2)
 {
-    HalfW<MULTI> w1;
-    if (len > (uint32_t)HALF)
-        seg_load_half<VEC, NTL, MULTI>(P, off, len, HALF, w1);
-    seg_sums_both<MULTI>(P, len, w0, w1, s0, s1, s2);
+    if (WHOLE || (P.S == (uint32_t)HALF && P.G == 1u)) {
+        // every segment is exactly HALF words (uniform): no second half and
+        // no select
+        double a[2] = {0.0, 0.0}, b[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < HALF; ++j) {
+            const double w = w0.at(j);
+            a[j & 1] += w;
+            b[j & 1] = fma((double)j, w, b[j & 1]);
+            c[j & 1] = fma((double)(j * j), w, c[j & 1]);
+        }
+        s0 = a[0] + a[1];
+        s1 = b[0] + b[1];
+        s2 = c[0] + c[1];
+        return;
+    }
+    if constexpr (!WHOLE) {
+        HalfW<MULTI> w1;
+        if (len > (uint32_t)HALF)
+            seg_load_half<VEC, NTL, MULTI>(P, off, len, HALF, w1);
+        seg_sums_both<MULTI>(P, len, w0, w1, s0, s1, s2);
+    }
 }
 
 // Staged tile loads (plan flag `stage`: every operand contiguous over the
@@ -839,7 +859,8 @@ __device__ __forceinline__ void short_sums(uint32_t len, const float v[SHORT_W],
 // STG: 0 per-lane segment loads; 1 staged tile loads of rows of 4, 8 or 16
 // words; 2 staged loads of 32-word segments (both halves); 3 short segments
 // (at most 8 words, one operand), SHORT_TILES tiles per pass; 4 row blocks
-// (16-word segments of whole short rows, staged).
+// (16-word segments of whole short rows, staged); 5 per-lane loads of
+// segments of exactly 16 words (rows of 16 words).
 template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true, int STG = 0>
 __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void moments_kernel(const SegPlan plan)
 {
@@ -935,7 +956,7 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
             if constexpr (STG == 2)
                 seg_sums_both<MULTI>(P, sg.len, w0, w1, s0, s1, s2);
             else
-                seg_sums_fma<VEC, NTL, MULTI>(P, off, sg.len, w0, s0, s1, s2);
+                seg_sums_fma<VEC, NTL, MULTI, STG == 5>(P, off, sg.len, w0, s0, s1, s2);
             seg_fold<DM, COV>(P, sg, s0, s1, s2, cin, acc);
         }
     }
@@ -1596,6 +1617,14 @@ static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
         case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, 1>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
         default: return hipErrorInvalidValue;   // the plan stages whole-quad rows only
         }
+    } else if (L.plan.stage == 5) {   // rows of exactly 16 words, per-lane loads
+        switch (k) {
+        case 7: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, false, 5>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 6: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, true, 5>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 5: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false, 5>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, 5>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        default: return hipErrorInvalidValue;   // the plan takes whole-quad rows only
+        }
     } else if (L.plan.stage == 4) {   // row blocks, one operand, two axes or more (the plan's rule)
         if constexpr (DM >= 2) {
             if (cached)
@@ -1736,10 +1765,11 @@ template <class K> static int occupancy(K kernel)
 
 template <int DM, bool COV> static int occ_moments(bool vec4, int stage)
 {
-    static int cache[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
-    int &c = cache[vec4 ? 1 : 0][stage < 5 ? stage : 0];
+    static int cache[2][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
+    int &c = cache[vec4 ? 1 : 0][stage < 6 ? stage : 0];
     if (!c) {
         switch (stage) {
+        case 5: c = occupancy(moments_kernel<DM, COV, true, false, true, 5>); break;
         case 4:
             if constexpr (DM >= 2)
                 c = occupancy(moments_kernel<DM, COV, true, false, true, 4>);

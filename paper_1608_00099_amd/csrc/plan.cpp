@@ -854,6 +854,10 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     // loads the segments of several tiles before folding them.
     if (r.op == TRIOT_OP_MOMENTS && n == 1 && L <= 8 && !P.stage)
         P.stage = 3u;
+    // Rows of exactly 16 words otherwise (per-lane loads): an instance
+    // without the second-half path of longer segments.
+    if (r.op == TRIOT_OP_MOMENTS && vec4 && L == 16 && !P.stage)
+        P.stage = 5u;
     // Rows of 2, 4 or 8 words laid end to end, one operand, the next axis a
     // multiple of 16 / L: the moments pass takes segments of 16 / L whole
     // rows (16 words), so that the outer coordinates enter once per 16
