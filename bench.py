@@ -546,12 +546,23 @@ def extras(dev, only=None):
     return out
 
 
+def _read_flush(flush):
+    """A read over the 1 GiB scratch: evicts the caches like the write does,
+    but leaves no dirty lines whose write-back would compete with the next
+    kernel's reads."""
+    return lambda: flush.sum()
+
+
 def _cold_warm(fn, flush, nbytes):
-    """Median GPU time of fn after a 1 GiB write (cold) and right after
-    itself (warm), with the effective GB/s of nbytes."""
+    """Median GPU time of fn after a 1 GiB write (cold), after a 1 GiB read
+    (cold_clean: the same eviction without dirty lines left in the
+    memory-side cache) and right after itself (warm), with the effective
+    GB/s of nbytes."""
     c = event_ms(fn, pre=lambda: flush.fill_(0.0))
+    cc = event_ms(fn, pre=_read_flush(flush))
     w = event_ms(fn)
     return {"cold": dict(c, GBs=nbytes / c["median_ms"] / 1e6),
+            "cold_clean": dict(cc, GBs=nbytes / cc["median_ms"] / 1e6),
             "warm": dict(w, GBs=nbytes / w["median_ms"] / 1e6), "bytes": nbytes}
 
 
@@ -662,8 +673,10 @@ def _cfg3(dev, flush, out):
     nb = 4 * p.numel()
     o32, o64 = api.moments(p, cov=True)
     t_cold = event_ms(lambda: api.moments(p, cov=True), pre=lambda: flush.fill_(0.0))
+    t_clean = event_ms(lambda: api.moments(p, cov=True), pre=_read_flush(flush))
     t_warm = event_ms(lambda: api.moments(p, cov=True))
     out["cfg3_moments_cov"] = {"cold": dict(t_cold, GBs=nb / t_cold["median_ms"] / 1e6),
+                               "cold_clean": dict(t_clean, GBs=nb / t_clean["median_ms"] / 1e6),
                                "warm": dict(t_warm, GBs=nb / t_warm["median_ms"] / 1e6),
                                "bytes": nb}
     log("moments done")

@@ -402,6 +402,21 @@ __device__ __forceinline__ void marginal_kept(const MargPlan &P, uint32_t o, int
 
 typedef float mf4 __attribute__((ext_vector_type(4), aligned(4)));
 
+// The marginal walks read every operand word once: non-temporal loads.
+// Loads that allocate in the caches must first evict what is there, and
+// after a kernel that wrote a large buffer the memory-side cache holds its
+// dirty lines, whose write-back then competes with these reads (measured on
+// 16^6 after a 1 GiB write: 34.2 against 26.6 us with the cache clean).
+__device__ __forceinline__ mf4 mload4(const GLOBAL float *p)
+{
+    return __builtin_nontemporal_load((const GLOBAL mf4 *)p);
+}
+
+__device__ __forceinline__ float mload1(const GLOBAL float *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
 // Thread (o, p) adds part p of kept tuple o's reduced sub-box in
 // lexicographic order.  RD > 0: exactly RD reduced axes, known at compile
 // time (the odometer in registers); RD == 0: any number.  W = 4: the
@@ -473,13 +488,13 @@ __global__ __launch_bounds__(MARG_NT) void marginal_kernel(const MargPlan P)
                 if (k < n) {
                     const GLOBAL float *pk = (const GLOBAL float *)(uintptr_t)P.ptr[k];
                     if constexpr (W == 4) {
-                        const mf4 x = *(const GLOBAL mf4 *)(pk + (ok ? off[k] : P.base[k]));
+                        const mf4 x = mload4(pk + (ok ? off[k] : P.base[k]));
                         v[u][k][0] = x.x;
                         v[u][k][1] = x.y;
                         v[u][k][2] = x.z;
                         v[u][k][3] = x.w;
                     } else {
-                        v[u][k][0] = pk[ok ? off[k] : P.base[k]];
+                        v[u][k][0] = mload1(pk + (ok ? off[k] : P.base[k]));
                     }
                 }
             }
@@ -539,7 +554,7 @@ __global__ __launch_bounds__(MARG_NT) void marginal_inter_kernel(const MargPlan 
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (k < n)
-                    v[u][k] = ((const GLOBAL float *)(uintptr_t)P.ptr[k])[off[k] + (int64_t)ee];
+                    v[u][k] = mload1((const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k] + (int64_t)ee);
         }
 #pragma unroll
         for (int u = 0; u < LA; ++u) {
@@ -582,7 +597,7 @@ __global__ __launch_bounds__(MARG_NT) void marginal_cols_kernel(const MargPlan P
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (k < n) {
-                    const mf4 x = *(const GLOBAL mf4 *)((const GLOBAL float *)(uintptr_t)P.ptr[k] +
+                    const mf4 x = mload4((const GLOBAL float *)(uintptr_t)P.ptr[k] +
                                                        P.base[k] + 4 * (int64_t)q +
                                                        (int64_t)rr * P.rstride[k][0]);
                     v[u][k][0] = x.x;
@@ -636,7 +651,7 @@ __global__ __launch_bounds__(MARG_NT) void marginal_runs_kernel(const MargPlan P
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (k < n) {
-            const mf4 x = *(const GLOBAL mf4 *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k] +
+            const mf4 x = mload4((const GLOBAL float *)(uintptr_t)P.ptr[k] + off[k] +
                                                4 * (int64_t)c);
             v[k][0] = x.x;
             v[k][1] = x.y;
