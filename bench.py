@@ -567,16 +567,23 @@ def _cold_warm(fn, flush, nbytes):
 
 
 def _paper(dev, flush, out):
-    """The paper's four benchmarks (Section 3) at its shapes."""
+    """The paper's four benchmarks (Section 3) at its shapes (benchmarks 1
+    and 3 with the library autotuner's schedule, the default schedule's
+    figures beside them)."""
     import torch
     from paper_1608_00099_amd import api
+    from paper_1608_00099_amd import _lib as L
     big, small = (1 << 10, 1 << 9, 1 << 8), (1 << 9, 1 << 9, 1 << 5)
     # benchmark 1: crop (2^10, 2^9, 2^8) -> (2^9, 2^9, 2^5), float32 and float64
     for dt, name in ((torch.float32, "f32"), (torch.float64, "f64")):
         a = torch.rand(big, dtype=dt, device=dev)
         o = torch.empty(small, dtype=dt, device=dev)
         nb = 2 * prod(small) * a.element_size()
-        out["paper_b1_crop_" + name] = _cold_warm(lambda: api.copy_(o, a, counter=small), flush, nb)
+        fn = (lambda: api.copy_(o, a, counter=small))
+        default = _cold_warm(fn, flush, nb)
+        # the library's autotuner on this crop, then the same measurement
+        api.autotune(L.OP_COPY, [o, a], counter=small, params=L.CopyParams(a.element_size()))
+        out["paper_b1_crop_" + name] = dict(_cold_warm(fn, flush, nb), default_schedule=default)
         del a, o
     # benchmark 2: inner product over the shared tuples
     a = torch.rand(big, dtype=torch.float32, device=dev)
@@ -588,7 +595,10 @@ def _paper(dev, flush, out):
     x = torch.rand(xs, device=dev)
     y = torch.rand(ys, device=dev)
     z = torch.rand(zs, device=dev)
-    out["paper_b3_update"] = _cold_warm(lambda: api.xpyx_mz_(x, y, z), flush, 16 * prod(xs))
+    default = _cold_warm(lambda: api.xpyx_mz_(x, y, z), flush, 16 * prod(xs))
+    api.autotune(L.OP_XPYX_MZ, [x, y, z])
+    out["paper_b3_update"] = dict(_cold_warm(lambda: api.xpyx_mz_(x, y, z), flush, 16 * prod(xs)),
+                                  default_schedule=default)
     del x, y, z
     # benchmark 4: naive convolution of two (2^8, 2^3) float64 matrices
     l = torch.rand((256, 8), dtype=torch.float64, device=dev)
