@@ -177,6 +177,23 @@ __device__ __forceinline__ double row16_sum(double v)
     return v;
 }
 
+// Over the four lanes of a quad, lane q receives the sum of v[q] (a
+// reduce-scatter in two exchanges: with the lane two apart, each lane keeps
+// the pair of values whose index shares its bit 1 and hands over the other
+// pair; with the neighbour, it keeps the value whose index is its own lane
+// number).  Fixed order: deterministic.
+__device__ __forceinline__ double quad_scatter(const double v[4])
+{
+    const uint32_t q = threadIdx.x & 3u;
+    const bool b1 = (q & 2u) != 0u, b0 = (q & 1u) != 0u;
+    double k0 = b1 ? v[2] : v[0], k1 = b1 ? v[3] : v[1];
+    const double h0 = b1 ? v[0] : v[2], h1 = b1 ? v[1] : v[3];
+    k0 += dpp_f64<DPP_QUAD_XOR2, 0xF>(h0);
+    k1 += dpp_f64<DPP_QUAD_XOR2, 0xF>(h1);
+    const double k = b0 ? k1 : k0, h = b0 ? k0 : k1;
+    return k + dpp_f64<DPP_QUAD_XOR1, 0xF>(h);
+}
+
 // Sum over the 32 lanes of each half wave; the sum is valid in the half
 // wave's LAST lane (31 or 63).  Fixed order: deterministic.
 __device__ __forceinline__ double half_wave_sum(double v)
@@ -860,7 +877,8 @@ __device__ __forceinline__ void short_sums(uint32_t len, const float v[SHORT_W],
 // words; 2 staged loads of 32-word segments (both halves); 3 short segments
 // (at most 8 words, one operand), SHORT_TILES tiles per pass; 4 row blocks
 // (16-word segments of whole short rows, staged); 5 per-lane loads of
-// segments of exactly 16 words (rows of 16 words).
+// segments of exactly 16 words (rows of 16 words); 6 rows of 16 words laid
+// end to end, one operand, loaded as quads of 16 rows, row sums across lanes.
 template <int DM, bool COV, bool VEC, bool MULTI, bool NTL = true, int STG = 0>
 __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void moments_kernel(const SegPlan plan)
 {
@@ -899,6 +917,43 @@ __global__ __launch_bounds__(NT, (moments_min_blocks<DM, COV, MULTI>())) void mo
                     rowblock_sums<8, COV>(v, S);
                 rowblock_fold<DM, COV>(P, (uint32_t)s * P.rb, S, cin, acc);
             }
+        }
+    } else if constexpr (STG == 6) {
+        // Rows of 16 words laid end to end, one operand: the wave's 64 rows
+        // of a tile are 4 KiB of consecutive memory.  Load k gives lane l
+        // quad l & 3 of row 16 k + l / 4 (each instruction covers 1 KiB,
+        // whole lines); the lane sums its four words for each k, and the
+        // quad's reduce-scatter leaves lane l the sums of row 16 (l & 3) +
+        // l / 4, which it folds.
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint32_t q = lane & 3u;
+        const GLOBAL f4v *src =
+            (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[0] + P.base[0]);
+        const double jq = (double)(4u * q);      // the lane's first column
+        for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
+            const uint64_t r0 = tile * NT + (threadIdx.x & ~63u) + (lane >> 2);
+            const uint64_t last = P.nseg - 1u;
+            f4v x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)         // rows past the end: the last row (never folded)
+                x[k] = ldg<NTL>(src + 4u * min(r0 + 16u * (uint32_t)k, last) + q);
+            double a[4], b[4], c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double w0 = (double)x[k].x, w1 = (double)x[k].y;
+                const double w2 = (double)x[k].z, w3 = (double)x[k].w;
+                // column j = 4q + e: sums of w, e w, e^2 w, then shifted by 4q
+                const double s0 = (w0 + w1) + (w2 + w3);
+                const double s1 = fma(3.0, w3, fma(2.0, w2, w1));
+                const double s2 = fma(9.0, w3, fma(4.0, w2, w1));
+                a[k] = s0;
+                b[k] = fma(jq, s0, s1);
+                c[k] = fma(jq, fma(jq, s0, 2.0 * s1), s2);
+            }
+            const double s0 = quad_scatter(a), s1 = quad_scatter(b), s2 = quad_scatter(c);
+            const uint64_t row = r0 + 16u * q;
+            if (row < P.nseg)
+                seg_fold<DM, COV>(P, Seg{(uint32_t)row, 0u, 16u}, s0, s1, s2, cin, acc);
         }
     } else if constexpr (STG == 3) {
         // block lb takes tiles lb*K .. lb*K + K-1, then (lb + g)*K .. (K
@@ -1617,6 +1672,12 @@ static hipError_t go_moments(const SegLaunch &L, hipStream_t st)
         case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, 1>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
         default: return hipErrorInvalidValue;   // the plan stages whole-quad rows only
         }
+    } else if (L.plan.stage == 6) {   // rows of 16 words end to end, one operand (the plan's rule)
+        switch (k) {
+        case 5: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, false, 6>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        case 4: hipLaunchKernelGGL((moments_kernel<DM, COV, true, false, true, 6>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
+        default: return hipErrorInvalidValue;
+        }
     } else if (L.plan.stage == 5) {   // rows of exactly 16 words, per-lane loads
         switch (k) {
         case 7: hipLaunchKernelGGL((moments_kernel<DM, COV, true, true, false, 5>), dim3(L.blocks), dim3(NT), 0, st, L.plan); break;
@@ -1765,10 +1826,11 @@ template <class K> static int occupancy(K kernel)
 
 template <int DM, bool COV> static int occ_moments(bool vec4, int stage)
 {
-    static int cache[2][6] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
-    int &c = cache[vec4 ? 1 : 0][stage < 6 ? stage : 0];
+    static int cache[2][7] = {{0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0}};
+    int &c = cache[vec4 ? 1 : 0][stage < 7 ? stage : 0];
     if (!c) {
         switch (stage) {
+        case 6: c = occupancy(moments_kernel<DM, COV, true, false, true, 6>); break;
         case 5: c = occupancy(moments_kernel<DM, COV, true, false, true, 5>); break;
         case 4:
             if constexpr (DM >= 2)

@@ -838,10 +838,11 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     P.vec4 = vec4 ? 1u : 0u;
     // Rows of 4, 8 or 16 words laid end to end: a wave's 64 segments are one
     // contiguous range, loaded line by line through LDS (inner product,
-    // bounding box; the moments pass for rows of 16 words from 2^21 rows
-    // on, measured faster there and slower below).
+    // bounding box; the moments pass over several operands for rows of 16
+    // words from 2^21 rows on, measured faster there and slower below).
     const bool stage_rows = full && vec4 && (L == 4 || L == 8 || L == 16);
-    const bool stage_moments = r.op == TRIOT_OP_MOMENTS && L == 16 && rows >= (int64_t(1) << 21);
+    const bool stage_moments =
+        r.op == TRIOT_OP_MOMENTS && n > 1 && L == 16 && rows >= (int64_t(1) << 21);
     P.stage = (stage_rows && (r.op == TRIOT_OP_DOT || r.op == TRIOT_OP_BBOX || stage_moments))
                   ? 1u : 0u;
     // Segments of 32 words laid end to end (rows a multiple of 32 words):
@@ -854,6 +855,12 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     // loads the segments of several tiles before folding them.
     if (r.op == TRIOT_OP_MOMENTS && n == 1 && L <= 8 && !P.stage)
         P.stage = 3u;
+    // Rows of 16 words laid end to end, one operand: every load instruction
+    // covers quads of 16 consecutive rows, and the row sums are formed across
+    // lanes (faster than the per-lane loads and than the LDS pass at every
+    // size measured, with 4 workgroups per CU).
+    if (r.op == TRIOT_OP_MOMENTS && n == 1 && full && vec4 && L == 16 && !P.stage)
+        P.stage = 6u;
     // Rows of exactly 16 words otherwise (per-lane loads): an instance
     // without the second-half path of longer segments.
     if (r.op == TRIOT_OP_MOMENTS && vec4 && L == 16 && !P.stage)
@@ -897,16 +904,19 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
         P.nterms = (uint32_t)(2 * dm);      // lo and hi + 1 per position (32-bit words)
 
     // Persistent grid: as many workgroups as can be resident at once (for
-    // the moments pass at most 2 per CU, 3 when staged: each workgroup ends
-    // in a reduction of every term, and measured on MI355X, 2 per CU beat 3
-    // and 4 on the per-lane loads).
+    // the moments pass at most 2 per CU, 3 when staged through LDS and 4 for
+    // the quads of 16-word rows: each workgroup ends in a reduction of every
+    // term, and measured on MI355X, 2 per CU beat 3 and 4 on the per-lane
+    // loads).
     const bool adj = r.op == TRIOT_OP_MOMENTS_ADJ;
     int bpc = 2;   // the inner product and the bounding box: 2 per CU
     if (r.op == TRIOT_OP_MOMENTS || adj)
         bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4, (int)P.stage);
-    // (the staged moments pass: 3 per CU, measured faster on large inputs)
+    // (the staged moments pass: 3 per CU, measured faster on large inputs;
+    // the quads of 16-word rows: 4, measured faster than 2 or 3 from 32 MiB
+    // of input up and level below)
     if (!adj)
-        bpc = std::min(bpc, (r.op == TRIOT_OP_MOMENTS && (P.stage == 1 || P.stage == 2 || P.stage == 4)) ? 3 : 2);
+        bpc = std::min(bpc, (r.op == TRIOT_OP_MOMENTS && P.stage == 6) ? 4 : ((r.op == TRIOT_OP_MOMENTS && (P.stage == 1 || P.stage == 2 || P.stage == 4)) ? 3 : 2));
     int64_t blocks = std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * bpc);
     if (blocks > 8)
         blocks = (blocks + 7) / 8 * 8;

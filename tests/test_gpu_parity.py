@@ -380,9 +380,9 @@ def test_moments_short_rows(shape, cov):
     _check_moments(host(o32), host(o64), want2, d, cov)
 
 
-# Rows of 16 words laid end to end from 2^21 rows on: the moments pass
-# takes the staged tile loads, 3 workgroups per CU (just below: per-lane
-# loads); one and two operands.
+# Rows of 16 words laid end to end from 2^21 rows on: one operand takes the
+# quads of 16-word rows (4 workgroups per CU), two operands the staged tile
+# loads (3 per CU; just below 2^21 rows, per-lane loads).
 @pytest.mark.parametrize("shape", [(2048, 1024, 16), (2047, 1024, 16), (8192, 257, 16)])
 def test_moments_large_staged(shape):
     announce("moments large staged", shape)
@@ -398,6 +398,25 @@ def test_moments_large_staged(shape):
         want = oracle.moments(shape, [p.reshape(-1), q.reshape(-1)], [shape, shape], cov=True)
         o32, o64 = api.moments(dev(p), cov=True, others=[dev(q)])
         _check_moments(host(o32), host(o64), want, d, True)
+
+
+# Rows of 16 words laid end to end, one operand: every load instruction
+# covers 16 consecutive rows and the row sums are formed across the lanes of
+# a quad.  Row counts that end the last wave after 1, 15, 17 or 63 of its 64
+# rows, several tiles, both accumulator tiers (10 axes: first moments only)
+# and both load hints.
+@pytest.mark.parametrize("shape", [(1, 16), (17, 16), (63, 16), (1041, 16), (3, 5, 67, 16),
+                                   (2, 3, 5, 7, 16), (2,) * 9 + (16,), (4099, 3, 16)])
+def test_moments_row_quads(shape):
+    announce("moments row quads", shape)
+    rng = inputs.rng(3, 27, len(shape), int(np.prod(shape)))
+    p = rng.gamma(0.5, 1.0, size=shape).astype(np.float32)
+    d = len(shape)
+    for cov in ((True, False) if d <= 8 else (False,)):
+        want = oracle.moments(shape, [p.reshape(-1)], [shape], cov=cov)
+        for cached in (False, True):
+            o32, o64 = api.moments(dev(p), cov=cov, cached=cached)
+            _check_moments(host(o32), host(o64), want, d, cov)
 
 
 # Rows a multiple of 32 words laid end to end: the moments pass stages both
