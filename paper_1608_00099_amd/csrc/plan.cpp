@@ -909,14 +909,24 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     // term, and measured on MI355X, 2 per CU beat 3 and 4 on the per-lane
     // loads).
     const bool adj = r.op == TRIOT_OP_MOMENTS_ADJ;
-    int bpc = 2;   // the inner product and the bounding box: 2 per CU
+    // The inner product and the bounding box: 2 per CU, 4 where each load
+    // instruction covers consecutive memory (the inner product's word quads
+    // and staged tiles, the bounding box's staged tiles, of 8-axis
+    // instances): each workgroup walks few tiles, and more workgroups keep
+    // more loads in flight (measured on MI355X: the inner product of a
+    // (2^9, 2^9, 2^5) window 34.0 -> 24.7 us, of two 16^6 operands 32.4 ->
+    // 28.8 us; the 16^6 bounding box 31.9 -> 27.9 us).
+    int bpc = 2;
+    if (D <= 8 && ((r.op == TRIOT_OP_DOT && (P.quads || P.stage == 1)) ||
+                   (r.op == TRIOT_OP_BBOX && P.stage == 1)))
+        bpc = 4;
     if (r.op == TRIOT_OP_MOMENTS || adj)
         bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4, (int)P.stage);
     // (the staged moments pass: 3 per CU, measured faster on large inputs;
     // the quads of 16-word rows: 4, measured faster than 2 or 3 from 32 MiB
     // of input up and level below)
-    if (!adj)
-        bpc = std::min(bpc, (r.op == TRIOT_OP_MOMENTS && P.stage == 6) ? 4 : ((r.op == TRIOT_OP_MOMENTS && (P.stage == 1 || P.stage == 2 || P.stage == 4)) ? 3 : 2));
+    if (r.op == TRIOT_OP_MOMENTS)
+        bpc = std::min(bpc, P.stage == 6 ? 4 : ((P.stage == 1 || P.stage == 2 || P.stage == 4) ? 3 : 2));
     int64_t blocks = std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * bpc);
     if (blocks > 8)
         blocks = (blocks + 7) / 8 * 8;
