@@ -209,6 +209,21 @@ __device__ __forceinline__ double wave_sum(double v)
     return v + dpp_f64<DPP_ROW_BCAST31, 0xC>(v);    // rows 2 and 3 add lane 31
 }
 
+// Minimum (MAX: maximum) over the 64 lanes of a wave by DPP, in the lane
+// pattern of wave_sum, valid in lane 63.  Lanes of rows that a step leaves
+// out receive the identity (all ones for the minimum, 0 for the maximum).
+template <bool MAX> __device__ __forceinline__ uint32_t wave_minmax(uint32_t v)
+{
+    constexpr int ID = MAX ? 0 : -1;
+    auto f = [](uint32_t a, int b) { return MAX ? max(a, (uint32_t)b) : min(a, (uint32_t)b); };
+    v = f(v, __builtin_amdgcn_update_dpp(ID, (int)v, DPP_QUAD_XOR1, 0xF, 0xF, false));
+    v = f(v, __builtin_amdgcn_update_dpp(ID, (int)v, DPP_QUAD_XOR2, 0xF, 0xF, false));
+    v = f(v, __builtin_amdgcn_update_dpp(ID, (int)v, DPP_HALF_MIRROR, 0xF, 0xF, false));
+    v = f(v, __builtin_amdgcn_update_dpp(ID, (int)v, DPP_ROW_MIRROR, 0xF, 0xF, false));
+    v = f(v, __builtin_amdgcn_update_dpp(ID, (int)v, DPP_ROW_BCAST15, 0xA, 0xF, false));
+    return f(v, __builtin_amdgcn_update_dpp(ID, (int)v, DPP_ROW_BCAST31, 0xC, 0xF, false));
+}
+
 // Workgroup sum of the per-thread terms acc[0..T) into dst[0..T), in a
 // fixed order.  Eight terms at a time pass through LDS transposed: thread t
 // stores its eight values at x[q][t]; then the 32 threads of half wave q sum
@@ -1548,20 +1563,17 @@ __global__ __launch_bounds__(NT, (W32 || DM > 8) ? 2 : 4) void bbox_kernel(const
             }
         }
     }
-    // fold the wave first (butterflies), then one LDS atomic per wave and
-    // position: 256 same-address atomics per position would serialize
+    // fold the wave first (DPP, into lane 63), then one LDS atomic per wave
+    // and position: 256 same-address atomics per position would serialize
 #pragma unroll
     for (int p = 0; p < DM; ++p) {
         if (p < D) {
-#pragma unroll
-            for (int k = 32; k >= 1; k >>= 1) {
-                lo[p] = min(lo[p], (uint32_t)__shfl_xor((int)lo[p], k, 64));
-                hi[p] = max(hi[p], (uint32_t)__shfl_xor((int)hi[p], k, 64));
-            }
+            lo[p] = wave_minmax<false>(lo[p]);
+            hi[p] = wave_minmax<true>(hi[p]);
         }
     }
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
+    if ((threadIdx.x & 63) == 63) {
 #pragma unroll
         for (int p = 0; p < DM; ++p) {
             if (p < D && hi[p]) {
@@ -1612,18 +1624,16 @@ __global__ __launch_bounds__(FNT) void bbox_final_kernel(const SegPlan P)
                 h[p] = partials[(size_t)(2 * p + 1) * nb + b];
             }
         }
-        // wave butterflies, then one LDS atomic per wave and position
+        // wave folds by DPP (into lane 63), then one LDS atomic per wave and
+        // position
 #pragma unroll
         for (int p = 0; p < DM; ++p) {
             if (p < D) {
-#pragma unroll
-                for (int k = 32; k >= 1; k >>= 1) {
-                    l[p] = min(l[p], (uint32_t)__shfl_xor((int)l[p], k, 64));
-                    h[p] = max(h[p], (uint32_t)__shfl_xor((int)h[p], k, 64));
-                }
+                l[p] = wave_minmax<false>(l[p]);
+                h[p] = wave_minmax<true>(h[p]);
             }
         }
-        if ((threadIdx.x & 63) == 0) {
+        if ((threadIdx.x & 63) == 63) {
 #pragma unroll
             for (int p = 0; p < DM; ++p) {
                 if (p < D && h[p]) {
