@@ -1776,7 +1776,12 @@ static void go_dot(const SegLaunch &L, hipStream_t st)
 
 hipError_t launch_dot(const SegLaunch &L, hipStream_t st)
 {
-    if (L.dm <= 8)
+    // the word-quad walk over at most 3 axes: an instance whose axis loops
+    // unroll to 3 (fewer run-time axis tests per quad; its other paths are
+    // never launched, they would spill)
+    if (L.plan.quads && L.plan.D <= 3)
+        go_dot<3>(L, st);
+    else if (L.dm <= 8)
         go_dot<8>(L, st);
     else
         go_dot<32>(L, st);
