@@ -118,7 +118,8 @@ struct SegPlan {
     uint32_t stage;           // 1, 2 tiles through LDS (rows of 4-16 words, 32-word segments); 3 short rows batched;
                               // 4 row blocks: segments of rb whole rows (16 words) through LDS;
                               // 5 rows of exactly 16 words, per-lane loads;
-                              // 6 rows of 16 words end to end, quads of 16 rows per load, sums across lanes
+                              // 6 rows of 16 words end to end, quads of 16 rows per load, row sums (moments)
+                              //   or row masks (bounding box) formed across lanes
     uint32_t rb;              // stage 4: rows per segment (16 / L)
     uint32_t quads;           // DOT: one word quad per lane (vec4, quads < 2^31, not staged)
     AxisDiv qdiv;             // quads: quad -> (row, quad in row), divisor L / 4

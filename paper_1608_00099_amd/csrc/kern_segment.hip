@@ -194,6 +194,20 @@ __device__ __forceinline__ double quad_scatter(const double v[4])
     return k + dpp_f64<DPP_QUAD_XOR1, 0xF>(h);
 }
 
+// quad_scatter's exchange pattern for 32-bit masks combined by OR: lane q
+// receives the OR of v[q] over its quad.
+__device__ __forceinline__ uint32_t quad_scatter_or(const uint32_t v[4])
+{
+    const uint32_t q = threadIdx.x & 3u;
+    const bool b1 = (q & 2u) != 0u, b0 = (q & 1u) != 0u;
+    uint32_t k0 = b1 ? v[2] : v[0], k1 = b1 ? v[3] : v[1];
+    const uint32_t h0 = b1 ? v[0] : v[2], h1 = b1 ? v[1] : v[3];
+    k0 |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h0, DPP_QUAD_XOR2, 0xF, 0xF, false);
+    k1 |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h1, DPP_QUAD_XOR2, 0xF, 0xF, false);
+    const uint32_t k = b0 ? k1 : k0, h = b0 ? k0 : k1;
+    return k | (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h, DPP_QUAD_XOR1, 0xF, 0xF, false);
+}
+
 // Sum over the 32 lanes of each half wave; the sum is valid in the half
 // wave's LAST lane (31 or 63).  Fixed order: deterministic.
 __device__ __forceinline__ double half_wave_sum(double v)
@@ -1493,6 +1507,53 @@ __global__ __launch_bounds__(NT, (W32 || DM > 8) ? 2 : 4) void bbox_kernel(const
     }
     const uint32_t lb = seg_logical_block();
     const uint64_t g = gridDim.x;
+    if (VEC && !W32 && P.stage == 6) {
+        // Rows of 16 words laid end to end: load r gives lane l quad l & 3 of
+        // row 16 r + l / 4 of the wave's 64 rows (1 KiB per instruction); the
+        // lane's 4-bit masks of its words, shifted to their columns, are
+        // combined across the quad so that lane l holds the 16-bit mask of
+        // row 16 (l & 3) + l / 4.
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint32_t q = lane & 3u;
+        for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
+            const uint64_t r0 = tile * NT + (threadIdx.x & ~63u) + (lane >> 2);
+            const uint64_t last = P.nseg - 1u;
+            uint32_t mk[4] = {0xFu, 0xFu, 0xFu, 0xFu};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k < (int)P.n) {
+                    const GLOBAL f4v *src =
+                        (const GLOBAL f4v *)((const GLOBAL float *)(uintptr_t)P.ptr[k] + P.base[k]);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {   // rows past the end: the last row (never folded)
+                        const f4v y = ldg<NTL>(src + 4u * min(r0 + 16u * (uint32_t)r, last) + q);
+                        mk[r] &= (y.x != 0.0f ? 1u : 0u) | (y.y != 0.0f ? 2u : 0u) |
+                                 (y.z != 0.0f ? 4u : 0u) | (y.w != 0.0f ? 8u : 0u);
+                    }
+                }
+            }
+            uint32_t v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                v[r] = mk[r] << (4u * q);
+            const uint32_t m = quad_scatter_or(v);
+            const uint64_t row = r0 + 16u * q;
+            if (row < P.nseg && m) {
+                double u[DM];
+                uint32_t tt[DM];
+                row_coords<DM>(P, (uint32_t)row, u, tt);
+                lo[0] = min(lo[0], (uint32_t)(__ffs(m) - 1));
+                hi[0] = max(hi[0], (uint32_t)(32 - __clz(m)));
+#pragma unroll
+                for (int p = 1; p < DM; ++p) {
+                    if (p < D) {
+                        lo[p] = min(lo[p], tt[p]);
+                        hi[p] = max(hi[p], tt[p] + 1u);
+                    }
+                }
+            }
+        }
+    } else
     for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
         const uint64_t s = tile * NT + threadIdx.x;
         uint32_t staged = 0xFFFFFFFFu;   // staged tiles: the nonzero mask of the segment

@@ -855,6 +855,11 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     // loads the segments of several tiles before folding them.
     if (r.op == TRIOT_OP_MOMENTS && n == 1 && L <= 8 && !P.stage)
         P.stage = 3u;
+    // The bounding box over rows of 16 words laid end to end: quads of 16
+    // consecutive rows per load instruction, the row masks combined across
+    // lanes (no LDS pass).
+    if (r.op == TRIOT_OP_BBOX && P.stage == 1 && L == 16)
+        P.stage = 6u;
     // Rows of 16 words laid end to end, one operand: every load instruction
     // covers quads of 16 consecutive rows, and the row sums are formed across
     // lanes (faster than the per-lane loads and than the LDS pass at every
@@ -918,7 +923,7 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     // 28.8 us; the 16^6 bounding box 31.9 -> 27.9 us).
     int bpc = 2;
     if (D <= 8 && ((r.op == TRIOT_OP_DOT && (P.quads || P.stage == 1)) ||
-                   (r.op == TRIOT_OP_BBOX && P.stage == 1)))
+                   (r.op == TRIOT_OP_BBOX && (P.stage == 1 || P.stage == 6))))
         bpc = 4;
     if (r.op == TRIOT_OP_MOMENTS || adj)
         bpc = segment_blocks_per_cu(adj, cov, adj ? dmax : dm, vec4, (int)P.stage);

@@ -320,11 +320,13 @@ def test_bbox_matches_oracle(case, density):
     assert np.array_equal(got, want), (got, want)
 
 
-# Rows of 4, 8 or 16 words laid end to end (the staged tile loads): one and
-# two operands, sparse and denser, and single nonzeros at the first and last
-# point (a ragged last wave).
+# Rows of 4, 8 or 16 words laid end to end (staged tile loads; rows of 16
+# words as quads of 16 rows per load, masks combined across lanes): one to
+# three operands, sparse and denser, and single nonzeros at the first and
+# last point (a ragged last wave: 1, 15, 17 or 63 of its 64 rows).
 @pytest.mark.parametrize("shape", [(7, 5, 16), (33, 29, 16), (300, 8), (5, 77, 4),
-                                   (2, 3, 1, 4, 3, 8), (65, 8, 16)])
+                                   (2, 3, 1, 4, 3, 8), (65, 8, 16), (1, 16), (17, 16),
+                                   (1041, 16), (2, 3, 5, 7, 16)])
 @pytest.mark.parametrize("density", [1e-3, 0.05])
 def test_bbox_short_rows(shape, density):
     announce("bbox short rows", shape, density)
@@ -333,7 +335,9 @@ def test_bbox_short_rows(shape, density):
     b = rng.standard_normal(shape).astype(np.float32)
     a[rng.random(shape) >= density] = 0.0
     b[rng.random(shape) >= 0.5] = 0.0
-    for ts in ([a], [a, b]):
+    c3 = rng.standard_normal(shape).astype(np.float32)
+    c3[rng.random(shape) >= 0.9] = 0.0
+    for ts in ([a], [a, b], [a, b, c3]):
         want = oracle.bbox(shape, ts, [shape] * len(ts))
         got = host(api.bbox(*[dev(t) for t in ts]))
         assert np.array_equal(got, want), (ts is None, got, want)
