@@ -501,9 +501,10 @@ __device__ __forceinline__ void seg_sums_fma(const SegPlan &P, const int64_t off
 // address unit then stalls on the L1 for about half of the moments pass.
 // Here lane i of load k takes word quad 64 k + i of the wave's range (each
 // instruction covers 1 KiB of consecutive memory, whole lines), writes it
-// to the wave's LDS rows, and reads its own segment back.  LDS rows are
-// padded to an odd number of quads (4, 12 or 20 words), which spreads the
-// per-lane 16-byte reads of eight lanes over all banks.
+// to the wave's LDS rows, and reads its own segment back (the inner product,
+// which needs only the total, adds the fetched quads directly).  LDS rows
+// are padded to an odd number of quads (4, 12 or 20 words), which spreads
+// the per-lane 16-byte reads of eight lanes over all banks.
 typedef float f4l __attribute__((ext_vector_type(4)));   // 16-byte aligned (LDS)
 constexpr int STG_ROW = 20;                              // LDS words per row at L = 16
 
@@ -1310,7 +1311,6 @@ __global__ __launch_bounds__(NT, 4) void dot_kernel(const SegPlan plan)
     SEG_PLAN_FOR(DM);
     __shared__ double xch[8][NT];
     __shared__ double tot[1];
-    __shared__ __align__(16) float stg[VEC ? NT / 64 : 1][VEC ? 64 * STG_ROW : 4];
     double acc[1] = {0.0};
     const uint32_t lb = seg_logical_block();
     const uint64_t g = gridDim.x;
@@ -1367,14 +1367,39 @@ __global__ __launch_bounds__(NT, 4) void dot_kernel(const SegPlan plan)
         for (uint64_t tile = lb; tile < P.ntiles; tile += g) {
             const uint64_t s = tile * NT + threadIdx.x;
             if (VEC && P.stage) {
-                HalfW<MULTI> w0;
-                stage_half<NTL, MULTI>(P, tile, (SHARED float *)stg[threadIdx.x >> 6], w0);
-                if (s < P.nseg) {
-                    const Seg sg = seg_of(P, s);
-                    const int64_t off[4] = {0, 0, 0, 0};   // no second half: len <= 16
-                    double s0, s1, s2;
-                    seg_moments<VEC, NTL, MULTI, 0>(P, off, sg.len, w0, s0, s1, s2);
-                    acc[0] += s0;
+                // every operand contiguous over the counter: only the total
+                // is needed, so each lane adds the products of the quads it
+                // fetched (no pass through LDS; the clamped copies past the
+                // wave's range are skipped)
+                const uint32_t cnt = stage_count(P, tile);
+                if (cnt) {
+                    const uint32_t lane = threadIdx.x & 63u;
+                    const uint32_t sh = stage_shift(P.S);
+                    const uint32_t nq = cnt << sh;
+                    // products formed in float64 in operand order
+                    float x[HALF];
+                    double w[HALF];
+                    stage_fetch<NTL>(P, 0, tile, x);
+#pragma unroll
+                    for (int j = 0; j < HALF; ++j)
+                        w[j] = (double)x[j];
+#pragma unroll
+                    for (int k = 1; k < 4; ++k) {
+                        if (MULTI && k < (int)P.n) {
+                            stage_fetch<NTL>(P, k, tile, x);
+#pragma unroll
+                            for (int j = 0; j < HALF; ++j)
+                                w[j] *= (double)x[j];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < HALF / 4; ++i) {
+                        if ((uint32_t)i < (1u << sh) && (uint32_t)i * 64u + lane < nq) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                acc[0] += w[4 * i + e];
+                        }
+                    }
                 }
             } else if (s < P.nseg) {
                 const Seg sg = seg_of(P, s);

@@ -837,9 +837,10 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
             vec4 = false;
     P.vec4 = vec4 ? 1u : 0u;
     // Rows of 4, 8 or 16 words laid end to end: a wave's 64 segments are one
-    // contiguous range, loaded line by line through LDS (inner product,
-    // bounding box; the moments pass over several operands for rows of 16
-    // words from 2^21 rows on, measured faster there and slower below).
+    // contiguous range, loaded line by line (the inner product adds the
+    // fetched quads directly; the bounding box and the moments pass over
+    // several operands, the latter for rows of 16 words from 2^21 rows on,
+    // measured faster there and slower below, pass them through LDS).
     const bool stage_rows = full && vec4 && (L == 4 || L == 8 || L == 16);
     const bool stage_moments =
         r.op == TRIOT_OP_MOMENTS && n > 1 && L == 16 && rows >= (int64_t(1) << 21);
@@ -916,7 +917,7 @@ triot_status plan_segment(const Request &r, int cus, SegLaunch *out)
     const bool adj = r.op == TRIOT_OP_MOMENTS_ADJ;
     // The inner product and the bounding box: 2 per CU, 4 where each load
     // instruction covers consecutive memory (the inner product's word quads
-    // and staged tiles, the bounding box's staged tiles, of 8-axis
+    // and tile loads, the bounding box's tile loads, of 8-axis
     // instances): each workgroup walks few tiles, and more workgroups keep
     // more loads in flight (measured on MI355X: the inner product of a
     // (2^9, 2^9, 2^5) window 34.0 -> 24.7 us, of two 16^6 operands 32.4 ->
