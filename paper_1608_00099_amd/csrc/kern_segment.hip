@@ -1376,8 +1376,10 @@ __global__ __launch_bounds__(NT, 4) void dot_kernel(const SegPlan plan)
                     const uint32_t lane = threadIdx.x & 63u;
                     const uint32_t sh = stage_shift(P.S);
                     const uint32_t nq = cnt << sh;
-                    // products formed in float64 in operand order
-                    float x[HALF];
+                    // products formed in float64 in operand order (rows of
+                    // 4 or 8 words fetch fewer than HALF words: the rest stay
+                    // zero and are never added)
+                    float x[HALF] = {};
                     double w[HALF];
                     stage_fetch<NTL>(P, 0, tile, x);
 #pragma unroll
