@@ -486,7 +486,7 @@ def test_dot_staged_rows(shape):
     b = rng.standard_normal(shape).astype(np.float32)
     c = rng.standard_normal(shape).astype(np.float32)
     n = int(np.prod(shape))
-    for ops in ([a, b], [a, b, c]):
+    for ops in ([a, b], [a, b, c], [a, b, c, a]):
         want = oracle.dot(shape, ops, [shape] * len(ops))
         mag = oracle.dot(shape, [np.abs(x) for x in ops], [shape] * len(ops))
         o32, o64 = api.dot(*[dev(x) for x in ops])
@@ -498,6 +498,10 @@ def test_dot_staged_rows(shape):
     bi = rng.integers(-3, 4, size=shape).astype(np.float32)
     want = oracle.dot(shape, [ai, bi], [shape, shape])
     o32, o64 = api.dot(dev(ai), dev(bi))
+    assert host(o64)[0] == want
+    ci = rng.integers(-2, 3, size=shape).astype(np.float32)
+    want = oracle.dot(shape, [ai, bi, ci, ai], [shape] * 4)
+    o32, o64 = api.dot(dev(ai), dev(bi), dev(ci), dev(ai))
     assert host(o64)[0] == want
 
 
@@ -528,6 +532,15 @@ def test_dot_quad_walk(case):
     bi = rng.integers(-3, 4, size=sb).astype(np.float32)
     want = oracle.dot(counter, [ai, bi], [sa, sb])
     o32, o64 = api.dot(dev(ai), dev(bi))
+    assert host(o64)[0] == want
+    # four operands over different windows (the intersection stays the
+    # counter), integer values: exact whatever the order
+    sc = tuple(x + 1 for x in counter)
+    sd = tuple(x + 4 for x in counter)
+    ci = rng.integers(-2, 3, size=sc).astype(np.float32)
+    di = rng.integers(-2, 3, size=sd).astype(np.float32)
+    want = oracle.dot(counter, [ai, bi, ci, di], [sa, sb, sc, sd])
+    o32, o64 = api.dot(dev(ai), dev(bi), dev(ci), dev(di))
     assert host(o64)[0] == want
 
 
